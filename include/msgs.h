@@ -1,0 +1,207 @@
+/*
+ * msgs.h -- C ABI of libmsgs, a selective multi-scale Gaussian-splatting
+ * rasteriser for AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Multi-Scale 3D Gaussian Splatting for Anti-Aliased Rendering"
+ * (Yan, Low, Chen, Lee; CVPR 2024).  A scene of 3D Gaussians, each tagged with
+ * a level of detail, is rendered at any resolution by the SelectiveRender
+ * procedure (Alg. 2): pixel coverage of every Gaussian (Sec. 4.1), the
+ * selection condition with the finest/coarsest exemptions (Sec. 4.2), an
+ * optional range update of S^max/S^min (Sec. 4.2), then the tile rasteriser of
+ * Sec. 3.1 (EWA splatting, 16x16 tiles, depth-sorted front-to-back blending).
+ * The backward pass is the exact adjoint of that forward for fixed discrete
+ * decisions.
+ *
+ * Conventions
+ *  - Plain C99.  Every pointer documented as "device" is a HIP device address
+ *    on the context's device; "host" pointers are ordinary CPU memory.
+ *  - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *    null stream).  Work is enqueued asynchronously on that stream unless the
+ *    call says it synchronises.
+ *  - Return value: MSGS_OK (0) or a negative MSGS_E_* code.  On error no output
+ *    is guaranteed, handles stay valid, and msgs_last_error() describes the
+ *    failure.
+ *  - Planar layout: a per-Gaussian quantity with c components is stored as c
+ *    planes of n floats (component-major), e.g. means[3][n].
+ *  - Camera: world->camera rotation R (row-major 3x3) and translation t, OpenCV
+ *    axes (x right, y down, z forward), pinhole intrinsics given at full
+ *    resolution.  A render at downscale d has W_d = floor(W/d), H_d =
+ *    floor(H/d) pixels and intrinsics divided by d; pixel (i, j) is sampled at
+ *    (i + 1/2, j + 1/2).
+ */
+#ifndef MSGS_H_
+#define MSGS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MSGS_VERSION 1
+
+#define MSGS_OK 0
+#define MSGS_E_INVALID (-1)  /* bad argument: null pointer, n < 0, downscale < 1, empty frame, ... */
+#define MSGS_E_NOMEM (-2)    /* device memory or the context's pool budget exhausted */
+#define MSGS_E_DEVICE (-3)   /* a HIP call failed; its text is in msgs_last_error() */
+#define MSGS_E_CAPACITY (-4) /* a fixed capacity (instances, views) was exceeded */
+#define MSGS_E_BUSY (-5)     /* a server queue is full */
+
+typedef struct msgs_context msgs_context;
+typedef struct msgs_scene msgs_scene;
+typedef struct msgs_frame msgs_frame;
+typedef struct msgs_server msgs_server;
+
+/* Scene description (Sec. 3.1 Gaussian record; Sec. 4.1 level; Sec. 4.2 stored
+ * coverage range).  All arrays have n entries per component:
+ *   means[3][n]     centres (world units)
+ *   scales[3][n]    per-axis standard deviations, linear, > 0
+ *   quats[4][n]     rotation quaternion (w, x, y, z), any non-zero length
+ *   opacity[n]      density sigma in [0, 1)
+ *   sh[(D+1)^2*3][n] spherical-harmonic colour, plane j*3 + c holds real SH
+ *                   coefficient j (j = l*l + l + m, orthonormal, no
+ *                   Condon-Shortley phase) of channel c; colour = max(0, sum + 1/2)
+ *   level[n]        level of detail, 0 = finest (creation downscale 4^level)
+ *   s_max[n], s_min[n]  stored pixel-coverage range (px); (0, +inf) means
+ *                   "never updated"
+ * sh_degree D in 0..3; n_levels L in 1..8 with level < L.
+ * ptrs_on_device: 1 if all pointers are device addresses, 0 if host. */
+typedef struct {
+  int64_t n;
+  int sh_degree;
+  int n_levels;
+  const float* means;
+  const float* scales;
+  const float* quats;
+  const float* opacity;
+  const float* sh;
+  const uint8_t* level;
+  float* s_max;
+  float* s_min;
+  int ptrs_on_device;
+} msgs_scene_desc;
+
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int width, height;
+} msgs_camera;
+
+/* Render options.
+ *   downscale    per-side factor d >= 1
+ *   selective    1: apply the selection condition of Sec. 4.2 with the level
+ *                exemptions; 0: render every Gaussian in front of the camera
+ *                (single-scale rendering)
+ *   update_range 1: after selection, apply the range update (decays 0.95 and
+ *                1.05, Sec. 4.2) to Gaussians in front of the camera whose
+ *                level l satisfies 4^l == downscale; writes the scene's
+ *                s_max/s_min in place
+ *   lowpass      screen-space dilation h (px^2) added to the projected
+ *                covariance, the merged kernel G_{V+V^h} of Sec. 3.2
+ *   near_z       near plane (camera-space z)
+ *   bg           background colour */
+typedef struct {
+  int downscale;
+  int selective;
+  int update_range;
+  float lowpass;
+  float near_z;
+  float bg[3];
+} msgs_render_opts;
+
+typedef struct {
+  int64_t n_gaussians;
+  int64_t n_selected;   /* in front and passing selection */
+  int64_t n_visible;    /* selected with at least one tile */
+  int64_t n_instances;  /* (Gaussian, tile) pairs */
+  int64_t n_blends;     /* accumulated contributions over all pixels */
+  int width, height, tiles_x, tiles_y;
+} msgs_stats;
+
+/* Gradient outputs, caller-owned device planar buffers with the scene's
+ * layout: dL/d means, dL/d scales (linear), dL/d quats (raw, un-normalised),
+ * dL/d opacity (sigma), dL/d sh.  Written, not accumulated; Gaussians that do
+ * not contribute get 0. */
+typedef struct {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacity;
+  float* sh;
+} msgs_grads;
+
+int msgs_version(void);
+/* Text of the last error on the calling thread; owned by the library. */
+const char* msgs_last_error(void);
+/* Fill `o` with the defaults: downscale 1, selective 1, update_range 0,
+ * lowpass 0.3, near_z 0.2, bg 0. */
+void msgs_default_opts(msgs_render_opts* o);
+
+/* Context: binds a HIP device and a device-memory budget (pool_bytes, 0 = no
+ * budget) shared by every frame it renders.  Destroy only after every scene,
+ * frame and server created from it. */
+int msgs_context_create(int device, size_t pool_bytes, msgs_context** out);
+int msgs_context_destroy(msgs_context* ctx);
+/* Bytes of device memory the context's frames and scenes hold right now. */
+int msgs_context_bytes_in_use(const msgs_context* ctx, size_t* out);
+
+/* Scene.  copy = 1: the library copies every array into HBM it owns (host or
+ * device sources; synchronous).  copy = 0: the device pointers are borrowed and
+ * must stay valid and unchanged-in-shape until msgs_scene_destroy; their
+ * contents may change between renders (training). */
+int msgs_scene_create(msgs_context* ctx, const msgs_scene_desc* d, int copy, msgs_scene** out);
+int msgs_scene_destroy(msgs_scene* s);
+/* Copy the scene's current s_max/s_min to host arrays of n floats (synchronous). */
+int msgs_scene_get_ranges(const msgs_scene* s, float* s_max_host, float* s_min_host);
+
+/* Render one view (Alg. 2 followed by the Sec. 3.1 rasteriser).
+ *   rgb_out   device [H_d][W_d][3] fp32, caller-owned
+ *   frame_out optional; receives the saved state needed by the backward pass
+ *             and the debug getters (release with msgs_frame_release).  The
+ *             scene must outlive the frame.
+ * The call synchronises `stream` once, to size the tile-instance buffers. */
+int msgs_render(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
+                const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
+                void* stream);
+
+/* Adjoint of msgs_render for the decisions taken in `frame` (selection, tiles,
+ * contributor lists, alpha and colour clamps, termination).
+ *   dL_drgb  device [H_d][W_d][3] fp32
+ *   out      device gradient planes (see msgs_grads)
+ * The scene's parameters must not have changed since the render.  The per-tile
+ * partial sums are reduced per Gaussian without atomics (deterministic). */
+int msgs_render_backward(msgs_context* ctx, const msgs_frame* frame, const float* dL_drgb,
+                         const msgs_grads* out, void* stream);
+
+/* Release a frame (its device memory is returned on the frame's stream). */
+int msgs_frame_release(msgs_frame* f);
+/* Statistics of a frame (synchronises the frame's stream). */
+int msgs_frame_stats(const msgs_frame* f, msgs_stats* out);
+
+/* Debug getters (synchronous, host outputs, caller-owned).
+ * selection: mask_host[n] = 1 for Gaussians in front and passing selection.
+ * keys: the sorted instance list, key = tile_id * 2^32 + IEEE bits of the
+ *   view-space depth, value = Gaussian index; ascending key, ties in ascending
+ *   index.  *n receives the count; arrays are filled only if cap >= count.
+ * state: per pixel [H_d][W_d] final transmittance and number of accumulated
+ *   contributions.
+ * ranges: per tile [tiles][2] half-open range in the sorted list, (0,0) when
+ *   empty; filled only if cap >= tiles. */
+int msgs_frame_get_selection(const msgs_frame* f, uint8_t* mask_host);
+int msgs_frame_get_keys(const msgs_frame* f, uint64_t* keys, uint32_t* vals, size_t cap,
+                        size_t* n);
+int msgs_frame_get_state(const msgs_frame* f, float* T_final, uint32_t* n_contrib);
+int msgs_frame_get_ranges(const msgs_frame* f, uint32_t* ranges, size_t cap, size_t* n);
+
+/* Device evaluation of the library's fp32 exp (domain [-5.6, 0]) and log
+ * (domain (1, 256)) used by selection and blending, on device arrays of n
+ * floats.  For verification of the numerics contract. */
+int msgs_debug_exp(const float* x, float* y, int64_t n, void* stream);
+int msgs_debug_log(const float* x, float* y, int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSGS_H_ */

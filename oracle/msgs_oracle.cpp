@@ -234,7 +234,8 @@ struct Proj {
   bool cclamp[3] = {false, false, false};
 };
 
-float clampf_to(float v, float lo, float hi) { return std::min(std::max(v, lo), hi); }
+// fmin/fmax semantics: a NaN operand yields the other operand.
+float clampf_to(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
 
 void project_one(const or_scene* s, const Cam& cam, const or_opts* o, int64_t k, Proj* P) {
   const int64_t n = s->n;
@@ -300,7 +301,7 @@ void project_one(const or_scene* s, const Cam& cam, const or_opts* o, int64_t k,
   P->lnq = P->vis ? log_spec(y255) : 0.0f;
   // pixel coverage: S^2 = 8 lnq det(V) / max(V11, V22)
   float det = P->V11 * P->V22 - P->V12 * P->V12;
-  float mx = std::max(P->V11, P->V22);
+  float mx = fmaxf(P->V11, P->V22);
   if (P->vis && det > 0.0f && mx > 0.0f) {
     float t8 = 8.0f * P->lnq;
     t8 = t8 * det;
@@ -416,7 +417,7 @@ PixOut composite(const std::vector<Proj>& P, const std::vector<int64_t>& L, int 
     if (power < -g.lq) continue;  // alpha is certainly below 1/255 here
     float ar = g.sigma * exp_spec(power);
     if (ar < kAlphaMin) continue;
-    float al = std::min(0.99f, ar);
+    float al = fminf(0.99f, ar);
     float Tn = T * (1.0f - al);
     if (Tn < 1e-4f) break;
     float wgt = al * T;
@@ -646,8 +647,8 @@ int or_update_range(const or_scene* s, const or_camera* c, const or_opts* o, flo
   if (lr < 0) return 0;
   for (int64_t k = 0; k < s->n; ++k) {
     if (!P[k].front || s->level[k] != lr) continue;
-    s_max[k] = std::max(0.95f * s_max[k], P[k].S);
-    s_min[k] = std::min(1.05f * s_min[k], P[k].S);
+    s_max[k] = fmaxf(0.95f * s_max[k], P[k].S);
+    s_min[k] = fminf(1.05f * s_min[k], P[k].S);
   }
   return 0;
 }

@@ -1,0 +1,74 @@
+// Host-side objects behind the opaque handles of msgs.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/msgs.h"
+#include "msgs_device.hpp"
+
+struct msgs_context {
+  int device = 0;
+  size_t budget = 0;                 // 0 = unlimited
+  std::atomic<size_t> in_use{0};     // bytes held by scenes and frames
+};
+
+struct msgs_scene {
+  msgs_context* ctx = nullptr;
+  msgs::SceneView view{};
+  std::vector<void*> owned;          // arrays the library allocated (copy = 1)
+  size_t owned_bytes = 0;
+};
+
+struct msgs_frame {
+  msgs_context* ctx = nullptr;
+  msgs_scene* scene = nullptr;
+  hipStream_t st = nullptr;
+  msgs::ViewParams v{};
+  msgs_render_opts opts{};
+  int64_t n = 0;
+  int64_t n_vis = 0;
+  int64_t n_inst = 0;
+  std::vector<std::pair<void*, size_t>> bufs;
+  // kept for the backward pass and the getters
+  unsigned long long* ctr = nullptr;   // [0] selected, [1] blends, [2] visible, [3] instances
+  uint8_t* sel = nullptr;
+  uint32_t* count = nullptr;
+  uint32_t* depthkey = nullptr;
+  msgs::Rec* rec = nullptr;
+  uint2* rect = nullptr;
+  uint32_t* emit_base = nullptr;
+  uint2* ranges = nullptr;
+  float* T_final = nullptr;
+  uint32_t* n_accum = nullptr;
+  uint32_t* n_last = nullptr;
+  uint32_t* tkeys = nullptr;
+  uint32_t* tvals = nullptr;
+  // temporaries of the render
+  uint32_t* blk_vis = nullptr;
+  uint32_t* blk_off = nullptr;
+  uint32_t* dkeys[2] = {nullptr, nullptr};
+  uint32_t* dvals[2] = {nullptr, nullptr};
+  uint32_t* vals_sorted = nullptr;
+  uint32_t* cnt_d = nullptr;
+  uint32_t* off_d = nullptr;
+  void* scan_tmp = nullptr;
+  void* sort_tmp = nullptr;
+};
+
+namespace msgs {
+extern thread_local std::string t_err;
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+int ctx_alloc(msgs_context* c, void** p, size_t bytes, hipStream_t st);
+void ctx_free(msgs_context* c, void* p, size_t bytes, hipStream_t st);
+int make_view(const msgs_camera* cam, const msgs_render_opts* o, int n_levels, ViewParams* v);
+int render_phase1(msgs_frame* f);
+int render_phase2(msgs_frame* f, float* rgb_out);
+void frame_free_all(msgs_frame* f);
+unsigned long long* pinned_slot();
+}  // namespace msgs

@@ -1,0 +1,311 @@
+"""Python binding of libmsgs (ctypes; argument marshalling only).
+
+Every step of the rasteriser runs in the HIP library.  PyTorch provides device
+memory (tensors' data pointers) and the stream (the current torch stream is
+passed to every call).  If the library is missing this module raises: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsgs.so")
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_CAPACITY, E_BUSY = 0, -1, -2, -3, -4, -5
+
+
+class MsgsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"msgs error {code}: {msg}")
+        self.code = code
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("sh_degree", C.c_int), ("n_levels", C.c_int),
+                ("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("level", C.c_void_p),
+                ("s_max", C.c_void_p), ("s_min", C.c_void_p), ("ptrs_on_device", C.c_int)]
+
+
+class CameraC(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("width", C.c_int), ("height", C.c_int)]
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("downscale", C.c_int), ("selective", C.c_int), ("update_range", C.c_int),
+                ("lowpass", C.c_float), ("near_z", C.c_float), ("bg", C.c_float * 3)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_gaussians", C.c_int64), ("n_selected", C.c_int64), ("n_visible", C.c_int64),
+                ("n_instances", C.c_int64), ("n_blends", C.c_int64), ("width", C.c_int),
+                ("height", C.c_int), ("tiles_x", C.c_int), ("tiles_y", C.c_int)]
+
+
+class Grads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("status", C.c_int), ("t_submit_us", C.c_double),
+                ("t_admit_us", C.c_double), ("t_start_us", C.c_double), ("t_done_us", C.c_double),
+                ("n_blends", C.c_int64)]
+
+
+_lib = None
+
+EXPORTS = {
+    "msgs_version": ([], C.c_int),
+    "msgs_last_error": ([], C.c_char_p),
+    "msgs_default_opts": ([C.c_void_p], None),
+    "msgs_context_create": ([C.c_int, C.c_size_t, C.c_void_p], C.c_int),
+    "msgs_context_destroy": ([C.c_void_p], C.c_int),
+    "msgs_context_bytes_in_use": ([C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_scene_create": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "msgs_scene_destroy": ([C.c_void_p], C.c_int),
+    "msgs_scene_get_ranges": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_render": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                     C.c_void_p], C.c_int),
+    "msgs_render_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_frame_release": ([C.c_void_p], C.c_int),
+    "msgs_frame_stats": ([C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_frame_get_selection": ([C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_frame_get_keys": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "msgs_frame_get_state": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_frame_get_ranges": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "msgs_debug_exp": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
+    "msgs_debug_log": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
+    "msgs_server_create": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "msgs_server_submit": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64], C.c_int),
+    "msgs_server_poll": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int], C.c_int),
+    "msgs_server_destroy": ([C.c_void_p], C.c_int),
+}
+
+
+def lib():
+    """Load libmsgs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libmsgs.so not found at {LIB_PATH}; run "
+                              f"python -m paper_2311_17089_amd.build (no fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in EXPORTS.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != OK:
+        raise MsgsError(rc, lib().msgs_last_error().decode(errors="replace"))
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def camera_c(cam) -> CameraC:
+    c = CameraC()
+    for i in range(9):
+        c.R[i] = float(np.float32(cam.R[i]))
+    for i in range(3):
+        c.t[i] = float(np.float32(cam.t[i]))
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def opts_c(downscale=1, selective=True, update_range=False, lowpass=0.3, near=0.2,
+           bg: Sequence[float] = (0.0, 0.0, 0.0)) -> RenderOpts:
+    o = RenderOpts()
+    o.downscale = int(downscale)
+    o.selective = 1 if selective else 0
+    o.update_range = 1 if update_range else 0
+    o.lowpass = float(lowpass)
+    o.near_z = float(near)
+    for i in range(3):
+        o.bg[i] = float(bg[i])
+    return o
+
+
+class Context:
+    def __init__(self, device: int = 0, pool_bytes: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        check(lib().msgs_context_create(device, pool_bytes, C.byref(h)))
+        self.h = h
+
+    def bytes_in_use(self) -> int:
+        v = C.c_size_t()
+        check(lib().msgs_context_bytes_in_use(self.h, C.byref(v)))
+        return int(v.value)
+
+    def close(self):
+        if self.h:
+            check(lib().msgs_context_destroy(self.h))
+            self.h = None
+
+
+class DeviceScene:
+    """A scene resident in HBM.  From a numpy `scenegen.Scene` the arrays are
+    uploaded as torch tensors and borrowed by the library (copy=0), so that the
+    torch tensors double as the parameters of the autograd path."""
+
+    FIELDS = ("means", "scales", "quats", "opacity", "sh", "level", "s_max", "s_min")
+
+    def __init__(self, ctx: Context, scene, device: Optional[torch.device] = None):
+        self.ctx = ctx
+        dev = device or torch.device("cuda", ctx.device)
+        self.n = int(scene.n)
+        self.sh_degree = int(scene.sh_degree)
+        self.n_levels = int(scene.n_levels)
+        self.t = {}
+        for k in self.FIELDS:
+            a = getattr(scene, k)
+            if isinstance(a, torch.Tensor):
+                t = a.to(dev).contiguous()
+            else:
+                t = torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+            self.t[k] = t
+        assert self.t["level"].dtype == torch.uint8
+        for k in self.FIELDS:
+            if k != "level":
+                assert self.t[k].dtype == torch.float32, k
+        d = SceneDesc(self.n, self.sh_degree, self.n_levels,
+                      *[self.t[k].data_ptr() for k in self.FIELDS], 1)
+        h = C.c_void_p()
+        check(lib().msgs_scene_create(ctx.h, C.byref(d), 0, C.byref(h)))
+        self.h = h
+
+    def ranges(self):
+        smax = np.empty(self.n, np.float32)
+        smin = np.empty(self.n, np.float32)
+        check(lib().msgs_scene_get_ranges(self.h, smax.ctypes.data, smin.ctypes.data))
+        return smax, smin
+
+    def close(self):
+        if self.h:
+            check(lib().msgs_scene_destroy(self.h))
+            self.h = None
+
+
+class Frame:
+    """Saved state of one render (for the backward pass and the getters)."""
+
+    def __init__(self, h, scene: DeviceScene, W: int, H: int):
+        self.h, self.scene, self.W, self.H = h, scene, W, H
+
+    def stats(self) -> dict:
+        s = Stats()
+        check(lib().msgs_frame_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def selection(self) -> np.ndarray:
+        m = np.empty(self.scene.n, np.uint8)
+        check(lib().msgs_frame_get_selection(self.h, m.ctypes.data))
+        return m
+
+    def keys(self):
+        n = C.c_size_t()
+        check(lib().msgs_frame_get_keys(self.h, None, None, 0, C.byref(n)))
+        k = np.empty(max(n.value, 1), np.uint64)
+        v = np.empty(max(n.value, 1), np.uint32)
+        check(lib().msgs_frame_get_keys(self.h, k.ctypes.data, v.ctypes.data, n.value, C.byref(n)))
+        return k[:n.value], v[:n.value]
+
+    def state(self):
+        T = np.empty((self.H, self.W), np.float32)
+        nc = np.empty((self.H, self.W), np.uint32)
+        check(lib().msgs_frame_get_state(self.h, T.ctypes.data, nc.ctypes.data))
+        return T, nc
+
+    def ranges(self) -> np.ndarray:
+        n = C.c_size_t()
+        check(lib().msgs_frame_get_ranges(self.h, None, 0, C.byref(n)))
+        r = np.empty((n.value, 2), np.uint32)
+        check(lib().msgs_frame_get_ranges(self.h, r.ctypes.data, n.value, C.byref(n)))
+        return r
+
+    def release(self):
+        if self.h:
+            check(lib().msgs_frame_release(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def render(ctx: Context, scene: DeviceScene, cam, downscale=1, selective=True,
+           update_range=False, lowpass=0.3, near=0.2, bg=(0.0, 0.0, 0.0), keep_frame=False,
+           out: Optional[torch.Tensor] = None, stream=None):
+    """Render one view; returns the image tensor [H_d, W_d, 3] (and the Frame
+    when keep_frame)."""
+    W, H = (cam.width // downscale, cam.height // downscale) if downscale >= 1 else (0, 0)
+    if out is None:
+        out = torch.empty((H, W, 3), dtype=torch.float32, device=torch.device("cuda", ctx.device))
+    assert out.is_contiguous() and out.dtype == torch.float32
+    if W > 0 and H > 0:
+        assert tuple(out.shape) == (H, W, 3), (tuple(out.shape), (H, W, 3))
+    c = camera_c(cam)
+    o = opts_c(downscale, selective, update_range, lowpass, near, bg)
+    fh = C.c_void_p()
+    check(lib().msgs_render(ctx.h, scene.h, C.byref(c), C.byref(o), C.c_void_p(out.data_ptr()),
+                            C.byref(fh) if keep_frame else None, C.c_void_p(_stream(stream))))
+    if keep_frame:
+        return out, Frame(fh, scene, W, H)
+    return out
+
+
+def render_backward(ctx: Context, frame: Frame, dL_drgb: torch.Tensor, stream=None) -> dict:
+    """Adjoint of `render` for the frame's decisions; returns gradient tensors
+    w.r.t. means, scales (linear), quats (raw), opacity and sh."""
+    sc = frame.scene
+    assert dL_drgb.is_contiguous() and dL_drgb.dtype == torch.float32
+    g = {k: torch.empty_like(sc.t[k]) for k in ("means", "scales", "quats", "opacity", "sh")}
+    gs = Grads(*[g[k].data_ptr() for k in ("means", "scales", "quats", "opacity", "sh")])
+    check(lib().msgs_render_backward(ctx.h, frame.h, C.c_void_p(dL_drgb.data_ptr()), C.byref(gs),
+                                     C.c_void_p(_stream(stream))))
+    return g
+
+
+def debug_exp(x: torch.Tensor, stream=None) -> torch.Tensor:
+    y = torch.empty_like(x)
+    check(lib().msgs_debug_exp(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), x.numel(),
+                               C.c_void_p(_stream(stream))))
+    return y
+
+
+def debug_log(x: torch.Tensor, stream=None) -> torch.Tensor:
+    y = torch.empty_like(x)
+    check(lib().msgs_debug_log(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), x.numel(),
+                               C.c_void_p(_stream(stream))))
+    return y
+
+
+def calibrate(ctx: Context, scene: DeviceScene, cams, near=0.2):
+    """Establish S^max/S^min on the device with the library's range update:
+    starting from (0, +inf), render level l at downscale 4^l for every camera."""
+    scene.t["s_max"].zero_()
+    scene.t["s_min"].fill_(float("inf"))
+    for l in range(scene.n_levels):
+        for cam in cams:
+            render(ctx, scene, cam, downscale=4 ** l, update_range=True, near=near)
+    torch.cuda.synchronize()
