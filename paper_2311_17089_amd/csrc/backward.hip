@@ -1,0 +1,395 @@
+// Backward pass: the exact adjoint of the forward for its discrete decisions.
+//
+//  k_blend_bwd   one workgroup per tile (XCD-aware order, as the forward).
+//                Each pixel replays its contributors back to front from the
+//                stored final transmittance (T_j = T_{j+1} / (1 - alpha_j)) and
+//                the suffix colour B_j; the nine partial derivatives of every
+//                instance (d u, d conic, d sigma, d colour) are summed over the
+//                tile's 256 pixels by DPP wave reductions and a four-wave LDS
+//                sum, and written once to the instance's emission slot.  No
+//                atomics: the result is deterministic.
+//  k_seg_small / k_seg_big   per-Gaussian sum of its contiguous emission
+//                range of partials (thread per Gaussian; workgroup per Gaussian
+//                with more than 64 tiles).
+//  k_chain       chain rule per Gaussian from (u, conic, sigma, colour) to the
+//                scene parameters (means, linear scales, raw quaternion,
+//                opacity, SH), recomputing the projection of the forward.
+#include "msgs_device.hpp"
+#include "msgs_kernels.hpp"
+
+namespace msgs {
+
+constexpr int kNP = 9;          // partials per instance
+constexpr uint32_t kSmallSeg = 64;
+
+// Sum of v over the 64 lanes of the wave, valid in lane 63 (DPP row sums,
+// then row broadcasts 15 and 31).
+__device__ __forceinline__ float wave_sum_to_63(float v) {
+  int x = __float_as_int(v);
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));  // quad_perm 1,0,3,2
+  x = __float_as_int(v);
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));  // quad_perm 2,3,0,1
+  x = __float_as_int(v);
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false)); // row_half_mirror
+  x = __float_as_int(v);
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false)); // row_mirror
+  x = __float_as_int(v);
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false)); // row_bcast15
+  x = __float_as_int(v);
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false)); // row_bcast31
+  return v;
+}
+
+__device__ __forceinline__ int xcd_tile_b(int b, int nblk) {
+  const int per = nblk >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+__global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const uint32_t* tvals,
+                                                      const Rec* rec, const uint2* rect,
+                                                      const uint32_t* emit_base, ViewParams v,
+                                                      int ntile, const float* T_final,
+                                                      const uint32_t* n_last, const float* dLdC,
+                                                      float* partial, int64_t ninst) {
+  __shared__ float4 s0[kBlock], s1[kBlock], s2[kBlock];
+  __shared__ uint32_t sslot[kBlock];
+  __shared__ float red[kNP][kBlock / 64][kBlock];
+  __shared__ uint32_t smax[kBlock / 64];
+  const int tile = xcd_tile_b(blockIdx.x, gridDim.x);
+  if (tile >= ntile) return;
+  const int tx = tile % v.Tx, ty = tile / v.Tx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
+  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const bool inside = px < v.W && py < v.H;
+  const float pcx = (float)px + 0.5f;
+  const float pcy = (float)py + 0.5f;
+  const uint2 rg = ranges[tile];
+  uint32_t last = 0;
+  float T = 1.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f;
+  if (inside) {
+    const int64_t pix = (int64_t)py * v.W + px;
+    last = n_last[pix];
+    T = T_final[pix];
+    d0 = dLdC[pix * 3 + 0];
+    d1 = dLdC[pix * 3 + 1];
+    d2 = dLdC[pix * 3 + 2];
+  }
+  float B0 = T * v.bg[0], B1 = T * v.bg[1], B2 = T * v.bg[2];
+  // largest contributor count in the tile
+  uint32_t wm = last;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) wm = max(wm, (uint32_t)__shfl_xor((int)wm, o, 64));
+  if (lane == 0) smax[wave] = wm;
+  __syncthreads();
+  uint32_t maxlast = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) maxlast = max(maxlast, smax[w]);
+  const int tw = (int)(v.Tx);
+  for (uint32_t hi = rg.x + maxlast; hi > rg.x;) {
+    const uint32_t lo = hi - rg.x > (uint32_t)kBlock ? hi - kBlock : rg.x;
+    const int nb = (int)(hi - lo);
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+      const uint32_t idx = hi - 1 - threadIdx.x;
+      const uint32_t k = tvals[idx];
+      const Rec r = rec[k];
+      s0[threadIdx.x] = r.r0;
+      s1[threadIdx.x] = r.r1;
+      s2[threadIdx.x] = r.r2;
+      const uint2 rr = rect[k];
+      const int xl = rr.x & 0xffff, xh = rr.x >> 16, yl = rr.y & 0xffff;
+      sslot[threadIdx.x] = emit_base[k] + (uint32_t)((ty - yl) * (xh - xl + 1) + (tx - xl));
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      const uint32_t pos = hi - 1 - (uint32_t)j - rg.x;  // position in the tile list
+      float g[kNP];
+      bool contrib = false;
+      if (pos < last) {
+        const float4 a = s0[j];
+        const float4 b = s1[j];
+        const float dx = pcx - a.x;
+        const float dy = pcy - a.y;
+        const float qx = dx * dx, qy = dy * dy, qxy = dx * dy;
+        const float e = -0.5f * (a.z * qx + b.x * qy);
+        const float power = e - a.w * qxy;
+        if (!(power > 0.0f || power < b.z)) {
+          const float ex = exp_c(power);
+          const float ar = b.y * ex;
+          if (!(ar < kAlphaMin)) {
+            contrib = true;
+            const float4 c = s2[j];
+            const float c0 = b.w, c1 = c.x, c2 = c.y;
+            const float al = fminf(kAlphaMax, ar);
+            const float om = 1.0f / (1.0f - al);
+            const float Tb = T * om;
+            const float w = al * Tb;
+            g[6] = d0 * w;
+            g[7] = d1 * w;
+            g[8] = d2 * w;
+            const float dal = d0 * (c0 * Tb - B0 * om) + d1 * (c1 * Tb - B1 * om) +
+                              d2 * (c2 * Tb - B2 * om);
+            B0 += c0 * w;
+            B1 += c1 * w;
+            B2 += c2 * w;
+            T = Tb;
+            const float dar = ar > kAlphaMax ? 0.0f : dal;
+            g[5] = dar * ex;
+            const float dp = dar * ar;
+            g[2] = dp * (-0.5f * qx);
+            g[3] = dp * (-qxy);
+            g[4] = dp * (-0.5f * qy);
+            g[0] = dp * (a.z * dx + a.w * dy);
+            g[1] = dp * (b.x * dy + a.w * dx);
+          }
+        }
+      }
+      if (__ballot(contrib)) {
+#pragma unroll
+        for (int q = 0; q < kNP; ++q) {
+          const float s = wave_sum_to_63(contrib ? g[q] : 0.0f);
+          if (lane == 63) red[q][wave][j] = s;
+        }
+      } else if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < kNP; ++q) red[q][wave][j] = 0.0f;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+      float s[kNP];
+      bool any = false;
+#pragma unroll
+      for (int q = 0; q < kNP; ++q) {
+        s[q] = (red[q][0][threadIdx.x] + red[q][1][threadIdx.x]) +
+               (red[q][2][threadIdx.x] + red[q][3][threadIdx.x]);
+        any = any || s[q] != 0.0f;
+      }
+      if (any) {
+        const int64_t slot = sslot[threadIdx.x];
+#pragma unroll
+        for (int q = 0; q < kNP; ++q) partial[q * ninst + slot] = s[q];
+      }
+    }
+    hi = lo;
+  }
+  (void)tw;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_f32(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+// Per-Gaussian sums of the partials over the emission range; Gaussians with
+// more than kSmallSeg tiles are queued for k_seg_big.
+__global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* count,
+                                                      const uint32_t* emit_base,
+                                                      const float* partial, int64_t ninst,
+                                                      int64_t n, float* gsum, uint32_t* big,
+                                                      uint32_t* nbig) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t c = count[k];
+  if (c > kSmallSeg) {
+    big[atomicAdd(nbig, 1u)] = (uint32_t)k;
+    return;
+  }
+  float s[kNP];
+#pragma unroll
+  for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
+  if (c > 0) {
+    const int64_t b = emit_base[k];
+    for (uint32_t i = 0; i < c; ++i)
+#pragma unroll
+      for (int q = 0; q < kNP; ++q) s[q] += partial[q * ninst + b + i];
+  }
+#pragma unroll
+  for (int q = 0; q < kNP; ++q) gsum[q * n + k] = s[q];
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
+                                                    const uint32_t* emit_base,
+                                                    const float* partial, int64_t ninst,
+                                                    int64_t n, float* gsum, const uint32_t* big,
+                                                    const uint32_t* nbig) {
+  __shared__ float wred[kNP][kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t m = *nbig;
+  for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const uint32_t k = big[i];
+    const uint32_t c = count[k];
+    const int64_t b = emit_base[k];
+    float s[kNP];
+#pragma unroll
+    for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
+    for (uint32_t t = threadIdx.x; t < c; t += kBlock)
+#pragma unroll
+      for (int q = 0; q < kNP; ++q) s[q] += partial[q * ninst + b + t];
+#pragma unroll
+    for (int q = 0; q < kNP; ++q) {
+      const float r = wave_sum_to_63(s[q]);
+      if (lane == 63) wred[q][wave] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNP) {
+      const int q = threadIdx.x;
+      gsum[q * n + k] = (wred[q][0] + wred[q][1]) + (wred[q][2] + wred[q][3]);
+    }
+    __syncthreads();
+  }
+}
+
+// Chain rule per Gaussian.
+__global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, const uint32_t* count,
+                                                  const float* gsum, float* g_means,
+                                                  float* g_scales, float* g_quats,
+                                                  float* g_opacity, float* g_sh) {
+  const int64_t n = s.n;
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const int D = s.sh_degree;
+  const int K = (D + 1) * (D + 1);
+  Geo g;
+  bool live = count[k] > 0 && project_geo(s, v, k, g);
+  if (!live) {
+    for (int i = 0; i < 3; ++i) g_means[i * n + k] = 0.0f;
+    for (int i = 0; i < 3; ++i) g_scales[i * n + k] = 0.0f;
+    for (int i = 0; i < 4; ++i) g_quats[i * n + k] = 0.0f;
+    g_opacity[k] = 0.0f;
+    for (int j = 0; j < K * 3; ++j) g_sh[(int64_t)j * n + k] = 0.0f;
+    return;
+  }
+  float G[kNP];
+#pragma unroll
+  for (int q = 0; q < kNP; ++q) G[q] = gsum[q * n + k];
+  const float gux = G[0], guy = G[1], gA11 = G[2], gA12 = G[3], gA22 = G[4];
+  g_opacity[k] = G[5];
+  // ---- colour -> SH coefficients and view direction
+  const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
+  float dv0 = mu0 - v.C[0], dv1 = mu1 - v.C[1], dv2 = mu2 - v.C[2];
+  const float dn = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
+  const float x = dv0 / dn, y = dv1 / dn, z = dv2 / dn;
+  float Y[16], Yx[16], Yy[16], Yz[16];
+  sh_eval(D, x, y, z, Y);
+  sh_grad(D, x, y, z, Yx, Yy, Yz);
+  float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
+  for (int c = 0; c < 3; ++c) {
+    float acc = 0.5f;
+    for (int j = 0; j < K; ++j) acc = acc + Y[j] * s.sh[(int64_t)(j * 3 + c) * n + k];
+    const float gc = acc < 0.0f ? 0.0f : G[6 + c];
+    for (int j = 0; j < K; ++j) {
+      const float f = s.sh[(int64_t)(j * 3 + c) * n + k];
+      g_sh[(int64_t)(j * 3 + c) * n + k] = Y[j] * gc;
+      gdx += gc * f * Yx[j];
+      gdy += gc * f * Yy[j];
+      gdz += gc * f * Yz[j];
+    }
+  }
+  // unit direction d = v / |v|: dL/dv = (g - d (d . g)) / |v|
+  const float dg = x * gdx + y * gdy + z * gdz;
+  float gm0 = (gdx - x * dg) / dn, gm1 = (gdy - y * dg) / dn, gm2 = (gdz - z * dg) / dn;
+  // ---- conic A = (V + hI)^-1 -> V
+  const float W11 = g.V11 + v.lowpass, W22 = g.V22 + v.lowpass, W12 = g.V12;
+  const float det2 = W11 * W22 - W12 * W12;
+  const float A11 = W22 / det2, A12 = -(W12 / det2), A22 = W11 / det2;
+  const float gV11 = -(gA11 * A11 * A11 + gA12 * A11 * A12 + gA22 * A12 * A12);
+  const float gV22 = -(gA11 * A12 * A12 + gA12 * A12 * A22 + gA22 * A22 * A22);
+  const float gV12 = -(2.0f * gA11 * A11 * A12 + gA12 * (A11 * A22 + A12 * A12) +
+                       2.0f * gA22 * A22 * A12);
+  // ---- V = Tm Sigma Tm^T -> Sigma and Tm
+  const float S00 = g.Sg[0], S01 = g.Sg[1], S02 = g.Sg[2], S11 = g.Sg[3], S12 = g.Sg[4],
+              S22 = g.Sg[5];
+  const float t0[3] = {g.Tm[0], g.Tm[1], g.Tm[2]};
+  const float t1[3] = {g.Tm[3], g.Tm[4], g.Tm[5]};
+  float St0[3], St1[3];
+  St0[0] = S00 * t0[0] + S01 * t0[1] + S02 * t0[2];
+  St0[1] = S01 * t0[0] + S11 * t0[1] + S12 * t0[2];
+  St0[2] = S02 * t0[0] + S12 * t0[1] + S22 * t0[2];
+  St1[0] = S00 * t1[0] + S01 * t1[1] + S02 * t1[2];
+  St1[1] = S01 * t1[0] + S11 * t1[1] + S12 * t1[2];
+  St1[2] = S02 * t1[0] + S12 * t1[1] + S22 * t1[2];
+  float gt0[3], gt1[3];
+  for (int i = 0; i < 3; ++i) {
+    gt0[i] = 2.0f * gV11 * St0[i] + gV12 * St1[i];
+    gt1[i] = gV12 * St0[i] + 2.0f * gV22 * St1[i];
+  }
+  // Gs = dL/dSigma + its transpose = 2 gV11 t0 t0^T + gV12 (t0 t1^T + t1 t0^T) + 2 gV22 t1 t1^T
+  float Gs[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      Gs[i][j] = 2.0f * gV11 * t0[i] * t0[j] + gV12 * (t0[i] * t1[j] + t1[i] * t0[j]) +
+                 2.0f * gV22 * t1[i] * t1[j];
+  // ---- Tm = J R -> J -> p (together with u)
+  const float* R = v.R;
+  const float gJ00 = gt0[0] * R[0] + gt0[1] * R[1] + gt0[2] * R[2];
+  const float gJ02 = gt0[0] * R[6] + gt0[1] * R[7] + gt0[2] * R[8];
+  const float gJ11 = gt1[0] * R[3] + gt1[1] * R[4] + gt1[2] * R[5];
+  const float gJ12 = gt1[0] * R[6] + gt1[1] * R[7] + gt1[2] * R[8];
+  const float px = g.p[0], py = g.p[1], pz = g.p[2];
+  const float iz = 1.0f / pz, iz2 = iz * iz, iz3 = iz2 * iz;
+  float gp0 = gJ02 * (-v.fx * iz2) + gux * v.fx * iz;
+  float gp1 = gJ12 * (-v.fy * iz2) + guy * v.fy * iz;
+  float gp2 = gJ00 * (-v.fx * iz2) + gJ02 * (2.0f * v.fx * px * iz3) + gJ11 * (-v.fy * iz2) +
+              gJ12 * (2.0f * v.fy * py * iz3) - gux * v.fx * px * iz2 - guy * v.fy * py * iz2;
+  // p = R mu + t -> mu
+  gm0 += R[0] * gp0 + R[3] * gp1 + R[6] * gp2;
+  gm1 += R[1] * gp0 + R[4] * gp1 + R[7] * gp2;
+  gm2 += R[2] * gp0 + R[5] * gp1 + R[8] * gp2;
+  g_means[k] = gm0;
+  g_means[n + k] = gm1;
+  g_means[2 * n + k] = gm2;
+  // ---- Sigma = M M^T, M = Q diag(s)
+  float M[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[i][j] = g.Q[i * 3 + j] * g.sc[j];
+  float gM[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) gM[i][j] = Gs[i][0] * M[0][j] + Gs[i][1] * M[1][j] + Gs[i][2] * M[2][j];
+  float gQ[9];
+  for (int j = 0; j < 3; ++j) {
+    g_scales[j * n + k] = gM[0][j] * g.Q[j] + gM[1][j] * g.Q[3 + j] + gM[2][j] * g.Q[6 + j];
+    for (int i = 0; i < 3; ++i) gQ[i * 3 + j] = gM[i][j] * g.sc[j];
+  }
+  // ---- Q(q_hat) -> q_hat -> raw q
+  const float w = g.qn[0], qx = g.qn[1], qy = g.qn[2], qz = g.qn[3];
+  const float gw = -2.0f * qz * gQ[1] + 2.0f * qy * gQ[2] + 2.0f * qz * gQ[3] - 2.0f * qx * gQ[5] -
+                   2.0f * qy * gQ[6] + 2.0f * qx * gQ[7];
+  const float gx = 2.0f * qy * gQ[1] + 2.0f * qz * gQ[2] + 2.0f * qy * gQ[3] - 4.0f * qx * gQ[4] -
+                   2.0f * w * gQ[5] + 2.0f * qz * gQ[6] + 2.0f * w * gQ[7] - 4.0f * qx * gQ[8];
+  const float gy = -4.0f * qy * gQ[0] + 2.0f * qx * gQ[1] + 2.0f * w * gQ[2] + 2.0f * qx * gQ[3] +
+                   2.0f * qz * gQ[5] - 2.0f * w * gQ[6] + 2.0f * qz * gQ[7] - 4.0f * qy * gQ[8];
+  const float gz = -4.0f * qz * gQ[0] - 2.0f * w * gQ[1] + 2.0f * qx * gQ[2] + 2.0f * w * gQ[3] -
+                   4.0f * qz * gQ[4] + 2.0f * qy * gQ[5] + 2.0f * qx * gQ[6] + 2.0f * qy * gQ[7];
+  const float dq = w * gw + qx * gx + qy * gy + qz * gz;
+  const float il = 1.0f / g.qlen;
+  g_quats[k] = (gw - w * dq) * il;
+  g_quats[n + k] = (gx - qx * dq) * il;
+  g_quats[2 * n + k] = (gy - qy * dq) * il;
+  g_quats[3 * n + k] = (gz - qz * dq) * il;
+}
+
+static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+void launch_backward(const BwdArgs& a, hipStream_t st) {
+  const int64_t n = a.s.n;
+  const int ntile = a.v.Tx * a.v.Ty;
+  const int nblk = (ntile + 7) / 8 * 8;
+  if (a.n_inst > 0) {
+    const int64_t m = (int64_t)kNP * a.n_inst;
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(m)), dim3(kBlock), 0, st, a.partial, m);
+    hipLaunchKernelGGL(k_blend_bwd, dim3(nblk), dim3(kBlock), 0, st, a.ranges, a.tvals, a.rec,
+                       a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last, a.dL_drgb, a.partial,
+                       a.n_inst);
+  }
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_seg_small, dim3(grid_for(n)), dim3(kBlock), 0, st, a.count, a.emit_base,
+                     a.partial, a.n_inst, n, a.gsum, a.big, a.nbig);
+  hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, a.partial,
+                     a.n_inst, n, a.gsum, a.big, a.nbig);
+  hipLaunchKernelGGL(k_chain, dim3(grid_for(n)), dim3(kBlock), 0, st, a.s, a.v, a.count, a.gsum,
+                     a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh);
+}
+
+}  // namespace msgs

@@ -447,6 +447,58 @@ int msgs_render(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
   return MSGS_OK;
 }
 
+int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_drgb,
+                         const msgs_grads* out, void* stream) {
+  if (!c || !f || !dL_drgb || !out) return fail(MSGS_E_INVALID, "null argument");
+  if (f->ctx != c) return fail(MSGS_E_INVALID, "frame belongs to another context");
+  const int64_t n = f->n;
+  if (n > 0 && (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh))
+    return fail(MSGS_E_INVALID, "null gradient array");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  struct Tmp {
+    void* p;
+    size_t b;
+  };
+  std::vector<Tmp> tmp;
+  auto alloc = [&](void** p, size_t bytes) {
+    int rc = ctx_alloc(c, p, bytes, st);
+    if (rc == MSGS_OK) tmp.push_back({*p, std::max<size_t>(bytes, 256)});
+    return rc;
+  };
+  BwdArgs a{};
+  a.s = f->scene->view;
+  a.v = f->v;
+  a.ranges = f->ranges;
+  a.tvals = f->tvals;
+  a.rec = f->rec;
+  a.rect = f->rect;
+  a.emit_base = f->emit_base;
+  a.count = f->count;
+  a.T_final = f->T_final;
+  a.n_last = f->n_last;
+  a.dL_drgb = dL_drgb;
+  a.n_inst = f->n_inst;
+  a.g_means = out->means;
+  a.g_scales = out->scales;
+  a.g_quats = out->quats;
+  a.g_opacity = out->opacity;
+  a.g_sh = out->sh;
+  int rc = alloc((void**)&a.partial, (size_t)9 * 4 * (size_t)f->n_inst);
+  if (rc == MSGS_OK) rc = alloc((void**)&a.gsum, (size_t)9 * 4 * (size_t)n);
+  if (rc == MSGS_OK) rc = alloc((void**)&a.big, (size_t)4 * (size_t)n);
+  if (rc == MSGS_OK) rc = alloc((void**)&a.nbig, 4);
+  if (rc == MSGS_OK) {
+    launch_fill_u32(a.nbig, 1, 0u, st);
+    launch_backward(a, st);
+    e = hipGetLastError();
+    if (e != hipSuccess) rc = hip_fail(e, "backward launch");
+  }
+  for (auto& t : tmp) ctx_free(c, t.p, t.b, st);
+  return rc;
+}
+
 int msgs_frame_release(msgs_frame* f) {
   if (!f) return fail(MSGS_E_INVALID, "null frame");
   (void)hipSetDevice(f->ctx->device);

@@ -54,8 +54,11 @@ struct BwdArgs {
   const float* T_final;
   const uint32_t* n_last;
   const float* dL_drgb;
-  float* partial;           // [9][n_inst]
+  float* partial;           // [9][n_inst] per-instance partials
   int64_t n_inst;
+  float* gsum;              // [9][n] per-Gaussian sums
+  uint32_t* big;            // [n] Gaussians with many tiles
+  uint32_t* nbig;           // device counter, zeroed by the caller
   float* g_means;
   float* g_scales;
   float* g_quats;

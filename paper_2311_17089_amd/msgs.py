@@ -309,3 +309,52 @@ def calibrate(ctx: Context, scene: DeviceScene, cams, near=0.2):
         for cam in cams:
             render(ctx, scene, cam, downscale=4 ** l, update_range=True, near=near)
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- autograd
+class _RenderFn(torch.autograd.Function):
+    """Differentiable render: forward and backward both run in libmsgs; the
+    scene is borrowed from the input tensors for the duration of the call."""
+
+    @staticmethod
+    def forward(fctx, means, scales, quats, opacity, sh, state):
+        ctx, level, s_max, s_min, n_levels, sh_degree, cam, kw = state
+        t = {"means": means.contiguous(), "scales": scales.contiguous(),
+             "quats": quats.contiguous(), "opacity": opacity.contiguous(),
+             "sh": sh.contiguous(), "level": level, "s_max": s_max, "s_min": s_min}
+        scene = _BorrowedScene(ctx, t, n_levels, sh_degree)
+        rgb, frame = render(ctx, scene, cam, keep_frame=True, **kw)
+        fctx.msgs = (ctx, scene, frame)
+        fctx.mark_non_differentiable()
+        return rgb
+
+    @staticmethod
+    def backward(fctx, grad_rgb):
+        ctx, scene, frame = fctx.msgs
+        g = render_backward(ctx, frame, grad_rgb.contiguous())
+        frame.release()
+        scene.close()
+        fctx.msgs = None
+        return g["means"], g["scales"], g["quats"], g["opacity"], g["sh"], None
+
+
+class _BorrowedScene(DeviceScene):
+    def __init__(self, ctx: Context, t: dict, n_levels: int, sh_degree: int):
+        self.ctx = ctx
+        self.t = t
+        self.n = int(t["opacity"].numel())
+        self.sh_degree = int(sh_degree)
+        self.n_levels = int(n_levels)
+        d = SceneDesc(self.n, self.sh_degree, self.n_levels,
+                      *[t[k].data_ptr() for k in self.FIELDS], 1)
+        h = C.c_void_p()
+        check(lib().msgs_scene_create(ctx.h, C.byref(d), 0, C.byref(h)))
+        self.h = h
+
+
+def render_differentiable(ctx: Context, means, scales, quats, opacity, sh, level, s_max, s_min,
+                          n_levels: int, sh_degree: int, cam, **kw) -> torch.Tensor:
+    """Image [H_d, W_d, 3] differentiable w.r.t. means [3,n], scales [3,n]
+    (linear), quats [4,n] (raw), opacity [n] (sigma) and sh [(D+1)^2*3, n]."""
+    return _RenderFn.apply(means, scales, quats, opacity, sh,
+                           (ctx, level, s_max, s_min, n_levels, sh_degree, cam, kw))
