@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Benchmark of the selective multi-scale Gaussian rasteriser on one MI355X.
+
+Workload: the 4-level synthetic scene (531,250 Gaussians; level l holds
+400k/4^l Gaussians, log-scale mean -4.5 + 1.4 l, SH degree 3), S^max/S^min
+established by the library's own range update over 8 seeded cameras, one
+1600x1064 camera at distance 3 (f = 1875).  One step = the whole hot path at
+the four downscales 1x, 4x, 16x, 64x with selective rendering: forward render
+(projection, coverage, selection, SH, binning, sorts, blending) and the
+backward pass against a fixed seeded dL/dRGB.  Inputs are resident in HBM
+before timing; the timed region is bracketed by device synchronisation.
+
+Metric: Gaussian-pixel blends per second (accumulated contributions of the
+forward renders of one step, divided by the step time).  The JSON line also
+carries per-downscale frame rates and p50/p99 frame latency for selective and
+single-scale (selection off) rendering, the roofline of the dominant kernel
+(live HIP-event timing of that kernel's launches) and the CPU oracle's rate on
+a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+DOWNSCALES = (1, 4, 16, 64)
+W_FULL, H_FULL, FOCAL = 1600, 1064, 1875.0
+HBM_PEAK_GBS = 8000.0
+# fp32 vector rate without packed math: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# x 2 flops per fma (packed fp32 is disabled in this build).
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# algorithmic fp32 flops of the compositing loop (fma = 2): every evaluated
+# (pixel, instance) pair costs the offset and quadratic form (11); every
+# accumulated contribution adds exp (19), alpha, transmittance and colour (10).
+FLOPS_PER_VISIT = 11
+FLOPS_PER_BLEND = 29
+STAGES = ("project", "depth_sort", "count_scan", "emit", "tile_sort", "ranges", "blend",
+          "blend_bwd", "chain_bwd")
+
+
+def c2_camera(G):
+    import numpy as np
+    return G.Camera(R=np.eye(3, dtype=np.float32).reshape(9), t=np.array([0, 0, 3], np.float32),
+                    fx=FOCAL, fy=FOCAL, cx=W_FULL / 2.0, cy=H_FULL / 2.0, width=W_FULL,
+                    height=H_FULL)
+
+
+def stage_bytes(st, n, sh_degree, passes_depth, passes_tile):
+    """Algorithmic HBM bytes of the memory-bound stages of one render."""
+    K = (sh_degree + 1) ** 2
+    nv, I = st["n_visible"], st["n_instances"]
+    ntile = st["tiles_x"] * st["tiles_y"]
+    return {
+        # read mu, s, q, sigma, level, S^max, S^min; write mask and tile count;
+        # visible: read SH, write record, rectangle, depth key, compacted pair
+        "project": n * (12 + 12 + 16 + 4 + 1 + 4 + 4) + n * (1 + 4) + nv * (12 * K + 48 + 8 + 4 + 8),
+        "depth_sort": passes_depth * nv * (4 + 16),
+        "count_scan": nv * (4 + 4 + 4),
+        "emit": nv * (4 + 4 + 8 + 4) + I * 8,
+        "tile_sort": passes_tile * I * (4 + 16),
+        "ranges": I * 4 + ntile * 8,
+        # partials written by the replay: 36 B per instance (plus the zero fill)
+        "blend_bwd_bytes": I * 36 * 2,
+        # read the partials and tile counts, write/read the per-Gaussian sums,
+        # read the parameters again, write every gradient plane
+        "chain_bwd": I * 36 + n * 8 + n * 72 + n * (53 + 12 * K) + n * (44 + 12 * K),
+    }
+
+
+def cpu_baseline(seconds_hint=True):
+    """The oracle as it stands, on a bounded sample of the workload: brute-force
+    compositing of 131072 random pixels of the 1x frame and of the whole 4x, 16x
+    and 64x frames (each call includes the oracle's projection of all
+    Gaussians).  Returns blends per second over the sample."""
+    import numpy as np
+    import oracle as O
+    from paper_2311_17089_amd import scenegen as G
+    sc = G.four_level_scene()
+    cal = O.calibrate(sc, G.calibration_cameras(1002, W_FULL, H_FULL, FOCAL))
+    cam = c2_camera(G)
+    rng = np.random.default_rng(7)
+    blends = 0
+    t0 = time.perf_counter()
+    for ds in DOWNSCALES:
+        W, H = W_FULL // ds, H_FULL // ds
+        if ds == 1:
+            idx = rng.choice(W * H, size=131072, replace=False)
+            pix = np.stack([idx % W, idx // W], 1).astype(np.int32)
+            _, _, nc = O.render_pixels(cal, cam, pix, downscale=ds)
+            blends += int(nc.sum())
+        else:
+            _, _, _, b = O.render(cal, cam, downscale=ds)
+            blends += b
+    dt = time.perf_counter() - t0
+    return {"value": blends / dt, "unit": "blends/s", "cores": int(O.lib().or_max_threads()),
+            "kind": "oracle",
+            "sample": "brute-force compositing of 131072 random pixels at 1x and of the full "
+                      "4x, 16x and 64x frames of the same scene and camera, selective, "
+                      f"{blends} blends in {dt:.1f} s (includes the oracle's per-call projection)"}
+
+
+def traffic_for(kernel, launch):
+    """HBM traffic of the dominant kernel from the committed rocprofv3 counter
+    summary, if it was taken from the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.loads(open(path).read().split("\n---\n")[0])
+    except Exception:
+        return None
+    ent = rec.get(kernel, {}).get(launch)
+    if not ent:
+        return None
+    src = os.path.join(ROOT, "paper_2311_17089_amd", "csrc", ent["source"])
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if h != ent["source_sha256_16"]:
+        return None
+    return ent["bytes_per_launch"]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-reps", type=int, default=30)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the hot path runs on a single MI355X and this build "
+              "has no multi-GPU path (see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2311_17089_amd import msgs as M
+    from paper_2311_17089_amd import scenegen as G
+
+    print("bench: building the 4-level scene", file=sys.stderr, flush=True)
+    ctx = M.Context(0)
+    sc = G.four_level_scene()
+    dsc = M.DeviceScene(ctx, sc)
+    M.calibrate(ctx, dsc, G.calibration_cameras(1002, W_FULL, H_FULL, FOCAL))
+    cam = c2_camera(G)
+    dls = {}
+    for i, ds in enumerate(DOWNSCALES):
+        g = torch.Generator().manual_seed(500 + i)
+        dls[ds] = torch.randn((H_FULL // ds, W_FULL // ds, 3), generator=g).cuda() * 1e-3
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for ds in DOWNSCALES:
+            _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True)
+            M.render_backward(ctx, fr, dls[ds])
+            fr.release()
+
+    # counts of one step (deterministic)
+    stats = {}
+    for ds in DOWNSCALES:
+        _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, profile=True)
+        M.render_backward(ctx, fr, dls[ds])
+        stats[ds] = fr.stats()
+        fr.release()
+    blends_per_step = sum(stats[ds]["n_blends"] for ds in DOWNSCALES)
+
+    print("bench: warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("bench: timed steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+
+    # live per-stage device time over the timed configuration (profiled steps)
+    prof_steps = max(3, min(args.steps, 10))
+    stage_tot = {s: 0.0 for s in STAGES}
+    per_ds_stage = {ds: {s: 0.0 for s in STAGES} for ds in DOWNSCALES}
+    for _ in range(prof_steps):
+        for ds in DOWNSCALES:
+            _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, profile=True)
+            M.render_backward(ctx, fr, dls[ds])
+            st = fr.stats()
+            fr.release()
+            for i, s in enumerate(STAGES):
+                per_ds_stage[ds][s] += st["stage_us"][i] / prof_steps
+                stage_tot[s] += st["stage_us"][i] / prof_steps
+    dominant = max(STAGES, key=lambda s: stage_tot[s])
+
+    # roofline of the dominant stage at its largest launch (the 1x frame)
+    st1 = stats[1]
+    us = per_ds_stage[1][dominant]
+    print("bench: stage us per step " + json.dumps({k: round(v, 1) for k, v in stage_tot.items()}),
+          file=sys.stderr, flush=True)
+    if dominant in ("blend", "blend_bwd"):
+        flops = FLOPS_PER_VISIT * st1["n_visits"] + FLOPS_PER_BLEND * st1["n_blends"]
+        achieved = flops / (us * 1e-6) / 1e12
+        roof = {"bound": "alu", "kernel": "k_blend" if dominant == "blend" else "k_blend_bwd",
+                "launch": "1x frame, selective", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
+                "algorithmic": f"{flops} flops = {FLOPS_PER_VISIT} x {st1['n_visits']} visits + "
+                               f"{FLOPS_PER_BLEND} x {st1['n_blends']} blends",
+                "avg_launch_us": us,
+                "traffic": traffic_for("k_blend" if dominant == "blend" else "k_blend_bwd", "1x")}
+    else:
+        ntile_bits = max(1, int(np.ceil(np.log2(max(2, st1["tiles_x"] * st1["tiles_y"])))))
+        b = stage_bytes(st1, sc.n, sc.sh_degree, 4, (ntile_bits + 7) // 8)[dominant]
+        achieved = b / (us * 1e-6) / 1e9
+        roof = {"bound": "hbm", "kernel": dominant, "launch": "1x frame, selective",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "algorithmic": f"{b} bytes",
+                "avg_launch_us": us, "traffic": traffic_for(dominant, "1x")}
+
+    # per-downscale frame rate and latency, selective vs single-scale (forward)
+    per_ds = {}
+    for ds in DOWNSCALES:
+        per_ds[str(ds)] = {}
+        for sel in (True, False):
+            for _ in range(2):
+                M.render(ctx, dsc, cam, downscale=ds, selective=sel)
+            torch.cuda.synchronize()
+            lat = []
+            for _ in range(args.latency_reps):
+                t = time.perf_counter()
+                M.render(ctx, dsc, cam, downscale=ds, selective=sel)
+                torch.cuda.synchronize()
+                lat.append((time.perf_counter() - t) * 1e3)
+            _, fr = M.render(ctx, dsc, cam, downscale=ds, selective=sel, keep_frame=True,
+                             profile=True)
+            s = fr.stats()
+            fr.release()
+            lat = np.array(lat)
+            per_ds[str(ds)]["selective" if sel else "single_scale"] = {
+                "fps": float(1e3 / lat.mean()), "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "device_ms": s["stage_us"][9] / 1e3,
+                "blends": s["n_blends"], "instances": s["n_instances"],
+                "selected": s["n_selected"], "blends_per_s": float(s["n_blends"] / lat.mean() * 1e3)}
+
+    out = {
+        "metric": "Gaussian-pixel blends/s",
+        "value": blends_per_step / (ms_per_step / 1e3),
+        "unit": "blends/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "4-level scene, 531,250 Gaussians (400k/4^l per level, SH degree 3), "
+                               "1600x1064 at 1x/4x/16x/64x, selective rendering, forward + backward "
+                               "per downscale",
+                   "n_gaussians": sc.n, "frames_per_step": len(DOWNSCALES),
+                   "blends_per_step": blends_per_step},
+        "roofline": roof,
+        "stage_us_per_step": {s: round(v, 2) for s, v in stage_tot.items()},
+        "per_downscale": per_ds,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    dsc.close()
+    del stream
+
+
+if __name__ == "__main__":
+    main()

@@ -101,7 +101,10 @@ typedef struct {
  *   lowpass      screen-space dilation h (px^2) added to the projected
  *                covariance, the merged kernel G_{V+V^h} of Sec. 3.2
  *   near_z       near plane (camera-space z)
- *   bg           background colour */
+ *   bg           background colour
+ *   profile      1: record HIP events between the pipeline stages on the
+ *                render stream (and on the backward's stream) so that
+ *                msgs_frame_stats can report per-stage device time */
 typedef struct {
   int downscale;
   int selective;
@@ -109,6 +112,7 @@ typedef struct {
   float lowpass;
   float near_z;
   float bg[3];
+  int profile;
 } msgs_render_opts;
 
 typedef struct {
@@ -117,7 +121,14 @@ typedef struct {
   int64_t n_visible;    /* selected with at least one tile */
   int64_t n_instances;  /* (Gaussian, tile) pairs */
   int64_t n_blends;     /* accumulated contributions over all pixels */
+  int64_t n_visits;     /* (pixel, instance) pairs the blend kernel evaluated */
   int width, height, tiles_x, tiles_y;
+  /* device time (us) per stage when rendered with profile = 1, else 0:
+   * [0] projection + selection + compaction  [1] depth sort  [2] tile-count scan
+   * [3] emission  [4] tile sort  [5] tile ranges  [6] blending
+   * [7] backward blend replay  [8] backward per-Gaussian sum + chain rule
+   * [9] whole forward (first to last stage, excluding the host wait) */
+  float stage_us[10];
 } msgs_stats;
 
 /* Gradient outputs, caller-owned device planar buffers with the scene's
@@ -136,7 +147,7 @@ int msgs_version(void);
 /* Text of the last error on the calling thread; owned by the library. */
 const char* msgs_last_error(void);
 /* Fill `o` with the defaults: downscale 1, selective 1, update_range 0,
- * lowpass 0.3, near_z 0.2, bg 0. */
+ * lowpass 0.3, near_z 0.2, bg 0, profile 0. */
 void msgs_default_opts(msgs_render_opts* o);
 
 /* Context: binds a HIP device and a device-memory budget (pool_bytes, 0 = no

@@ -1,0 +1,167 @@
+// Stream-ordered caching allocator of a context.
+//
+// Blocks come from hipMalloc and are never returned to the driver until the
+// context is destroyed or an allocation fails (then every idle block is freed
+// and the allocation retried).  A freed block records an event on the stream
+// that last used it: the same stream may take it again at once (stream order
+// protects the previous use); another stream takes it only once that event has
+// completed.  Sizes are rounded (powers of two up to 1 MiB, then eighths of the
+// next power of two) so that frames of similar size share blocks.  The
+// context's budget counts the rounded bytes of live blocks; that is the figure
+// the server's admission control reads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "msgs_internal.hpp"
+
+namespace msgs {
+
+namespace {
+size_t round_size(size_t b) {
+  b = std::max<size_t>(b, 512);
+  size_t p = 512;
+  while (p < b) p <<= 1;
+  if (p <= (1u << 20)) return p;
+  const size_t g = p >> 3;
+  return (b + g - 1) / g * g;
+}
+}  // namespace
+
+struct DeviceCache::Impl {
+  struct Free {
+    void* p;
+    hipStream_t st;
+    hipEvent_t ev;
+  };
+  std::mutex mu;
+  std::multimap<size_t, Free> free_;
+  std::unordered_map<void*, size_t> live_;
+  std::vector<hipEvent_t> events_;
+  size_t cached = 0;
+
+  hipEvent_t get_event() {
+    if (!events_.empty()) {
+      hipEvent_t e = events_.back();
+      events_.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+};
+
+DeviceCache::DeviceCache() : impl(new Impl()) {}
+
+DeviceCache::~DeviceCache() {
+  release_idle();
+  for (hipEvent_t e : impl->events_) (void)hipEventDestroy(e);
+  delete impl;
+}
+
+size_t DeviceCache::idle_bytes() {
+  std::lock_guard<std::mutex> g(impl->mu);
+  return impl->cached;
+}
+
+void DeviceCache::release_idle() {
+  (void)hipDeviceSynchronize();
+  std::lock_guard<std::mutex> g(impl->mu);
+  for (auto& kv : impl->free_) {
+    (void)hipFree(kv.second.p);
+    if (kv.second.ev) impl->events_.push_back(kv.second.ev);
+  }
+  impl->free_.clear();
+  impl->cached = 0;
+}
+
+int DeviceCache::alloc(msgs_context* c, void** out, size_t bytes, hipStream_t st) {
+  const size_t sz = round_size(bytes);
+  {
+    std::lock_guard<std::mutex> g(impl->mu);
+    if (c->budget && c->in_use.load() + sz > c->budget)
+      return fail(MSGS_E_NOMEM, "context memory budget exceeded (" +
+                                    std::to_string(c->in_use.load() + sz) + " > " +
+                                    std::to_string(c->budget) + " bytes)");
+    auto lo = impl->free_.lower_bound(sz);
+    auto hi = impl->free_.upper_bound(sz + sz / 2);
+    auto pick = impl->free_.end();
+    for (auto it = lo; it != hi; ++it) {
+      if (it->second.st == st) {
+        pick = it;
+        break;
+      }
+      if (pick == impl->free_.end() && it->second.ev && hipEventQuery(it->second.ev) == hipSuccess)
+        pick = it;
+    }
+    if (pick != impl->free_.end()) {
+      *out = pick->second.p;
+      const size_t bsz = pick->first;
+      if (pick->second.ev) impl->events_.push_back(pick->second.ev);
+      impl->cached -= bsz;
+      impl->free_.erase(pick);
+      impl->live_[*out] = bsz;
+      c->in_use += bsz;
+      return MSGS_OK;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release_idle();
+    e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MSGS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+  }
+  std::lock_guard<std::mutex> g(impl->mu);
+  impl->live_[p] = sz;
+  c->in_use += sz;
+  *out = p;
+  return MSGS_OK;
+}
+
+void DeviceCache::free(msgs_context* c, void* p, hipStream_t st) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(impl->mu);
+  auto it = impl->live_.find(p);
+  if (it == impl->live_.end()) return;
+  const size_t sz = it->second;
+  impl->live_.erase(it);
+  c->in_use -= sz;
+  hipEvent_t ev = impl->get_event();
+  if (ev && hipEventRecord(ev, st) != hipSuccess) {
+    (void)hipGetLastError();
+    impl->events_.push_back(ev);
+    ev = nullptr;
+  }
+  impl->free_.insert({sz, Impl::Free{p, st, ev}});
+  impl->cached += sz;
+}
+
+// ---------------------------------------------------------------- carving
+size_t Carve::add(void** slot, size_t bytes) {
+  const size_t off = total;
+  total += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+  parts.push_back({slot, off});
+  return off;
+}
+
+int Carve::alloc(msgs_context* c, hipStream_t st) {
+  int rc = c->cache.alloc(c, &base, total, st);
+  if (rc != MSGS_OK) return rc;
+  for (auto& p : parts) *p.first = (char*)base + p.second;
+  return MSGS_OK;
+}
+
+}  // namespace msgs

@@ -9,8 +9,10 @@
 //                sum, and written once to the instance's emission slot.  No
 //                atomics: the result is deterministic.
 //  k_seg_small / k_seg_big   per-Gaussian sum of its contiguous emission
-//                range of partials (thread per Gaussian; workgroup per Gaussian
-//                with more than 64 tiles).
+//                range of partials.  Threads walk the Gaussians in emission
+//                (depth) order so that a wave reads one contiguous span; a
+//                Gaussian with more than 64 tiles gets a workgroup.  Partials and
+//                sums are stored as three float4 per instance / Gaussian.
 //  k_chain       chain rule per Gaussian from (u, conic, sigma, colour) to the
 //                scene parameters (means, linear scales, raw quaternion,
 //                opacity, SH), recomputing the projection of the forward.
@@ -20,6 +22,7 @@
 namespace msgs {
 
 constexpr int kNP = 9;          // partials per instance
+constexpr int kBB = 128;        // instances per LDS batch of the replay
 constexpr uint32_t kSmallSeg = 64;
 
 // Sum of v over the 64 lanes of the wave, valid in lane 63 (DPP row sums,
@@ -51,9 +54,9 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
                                                       int ntile, const float* T_final,
                                                       const uint32_t* n_last, const float* dLdC,
                                                       float* partial, int64_t ninst) {
-  __shared__ float4 s0[kBlock], s1[kBlock], s2[kBlock];
-  __shared__ uint32_t sslot[kBlock];
-  __shared__ float red[kNP][kBlock / 64][kBlock];
+  __shared__ float4 s0[kBB], s1[kBB], s2[kBB];
+  __shared__ uint32_t sslot[kBB];
+  __shared__ float red[kNP][kBlock / 64][kBB];
   __shared__ uint32_t smax[kBlock / 64];
   const int tile = xcd_tile_b(blockIdx.x, gridDim.x);
   if (tile >= ntile) return;
@@ -87,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
   for (int w = 0; w < kBlock / 64; ++w) maxlast = max(maxlast, smax[w]);
   const int tw = (int)(v.Tx);
   for (uint32_t hi = rg.x + maxlast; hi > rg.x;) {
-    const uint32_t lo = hi - rg.x > (uint32_t)kBlock ? hi - kBlock : rg.x;
+    const uint32_t lo = hi - rg.x > (uint32_t)kBB ? hi - kBB : rg.x;
     const int nb = (int)(hi - lo);
     __syncthreads();
     if ((int)threadIdx.x < nb) {
@@ -167,9 +170,10 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
         any = any || s[q] != 0.0f;
       }
       if (any) {
-        const int64_t slot = sslot[threadIdx.x];
-#pragma unroll
-        for (int q = 0; q < kNP; ++q) partial[q * ninst + slot] = s[q];
+        float4* P = (float4*)partial + (int64_t)sslot[threadIdx.x] * 3;
+        P[0] = make_float4(s[0], s[1], s[2], s[3]);
+        P[1] = make_float4(s[4], s[5], s[6], s[7]);
+        P[2] = make_float4(s[8], 0.0f, 0.0f, 0.0f);
       }
     }
     hi = lo;
@@ -177,65 +181,75 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
   (void)tw;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill_f32(float* p, int64_t n) {
+__global__ __launch_bounds__(kBlock) void k_fill_f4(float4* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = 0.0f;
+  if (i < n) p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-// Per-Gaussian sums of the partials over the emission range; Gaussians with
-// more than kSmallSeg tiles are queued for k_seg_big.
-__global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* count,
+__device__ __forceinline__ void acc3(float* s, const float4* P) {
+  const float4 a = P[0], b = P[1], c = P[2];
+  s[0] += a.x; s[1] += a.y; s[2] += a.z; s[3] += a.w;
+  s[4] += b.x; s[5] += b.y; s[6] += b.z; s[7] += b.w;
+  s[8] += c.x;
+}
+
+__device__ __forceinline__ void store3(float* gsum, int64_t k, const float* s) {
+  float4* G = (float4*)gsum + k * 3;
+  G[0] = make_float4(s[0], s[1], s[2], s[3]);
+  G[1] = make_float4(s[4], s[5], s[6], s[7]);
+  G[2] = make_float4(s[8], 0.0f, 0.0f, 0.0f);
+}
+
+// Per-Gaussian sums of the partials over the emission range, Gaussians in
+// emission order; those with more than kSmallSeg tiles are queued for
+// k_seg_big.
+__global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int64_t n_vis,
+                                                      const uint32_t* count,
                                                       const uint32_t* emit_base,
-                                                      const float* partial, int64_t ninst,
-                                                      int64_t n, float* gsum, uint32_t* big,
-                                                      uint32_t* nbig) {
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
+                                                      const float* partial, float* gsum,
+                                                      uint32_t* big, uint32_t* nbig) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= n_vis) return;
+  const uint32_t k = order[j];
   const uint32_t c = count[k];
   if (c > kSmallSeg) {
-    big[atomicAdd(nbig, 1u)] = (uint32_t)k;
+    big[atomicAdd(nbig, 1u)] = k;
     return;
   }
   float s[kNP];
 #pragma unroll
   for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
-  if (c > 0) {
-    const int64_t b = emit_base[k];
-    for (uint32_t i = 0; i < c; ++i)
-#pragma unroll
-      for (int q = 0; q < kNP; ++q) s[q] += partial[q * ninst + b + i];
-  }
-#pragma unroll
-  for (int q = 0; q < kNP; ++q) gsum[q * n + k] = s[q];
+  const float4* P = (const float4*)partial + (int64_t)emit_base[k] * 3;
+  for (uint32_t i = 0; i < c; ++i) acc3(s, P + 3 * i);
+  store3(gsum, k, s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
                                                     const uint32_t* emit_base,
-                                                    const float* partial, int64_t ninst,
-                                                    int64_t n, float* gsum, const uint32_t* big,
-                                                    const uint32_t* nbig) {
+                                                    const float* partial, float* gsum,
+                                                    const uint32_t* big, const uint32_t* nbig) {
   __shared__ float wred[kNP][kBlock / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t m = *nbig;
   for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
     const uint32_t k = big[i];
     const uint32_t c = count[k];
-    const int64_t b = emit_base[k];
+    const float4* P = (const float4*)partial + (int64_t)emit_base[k] * 3;
     float s[kNP];
 #pragma unroll
     for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
-    for (uint32_t t = threadIdx.x; t < c; t += kBlock)
-#pragma unroll
-      for (int q = 0; q < kNP; ++q) s[q] += partial[q * ninst + b + t];
+    for (uint32_t t = threadIdx.x; t < c; t += kBlock) acc3(s, P + 3 * t);
 #pragma unroll
     for (int q = 0; q < kNP; ++q) {
       const float r = wave_sum_to_63(s[q]);
       if (lane == 63) wred[q][wave] = r;
     }
     __syncthreads();
-    if (threadIdx.x < kNP) {
-      const int q = threadIdx.x;
-      gsum[q * n + k] = (wred[q][0] + wred[q][1]) + (wred[q][2] + wred[q][3]);
+    if (threadIdx.x == 0) {
+      float r[kNP];
+#pragma unroll
+      for (int q = 0; q < kNP; ++q) r[q] = (wred[q][0] + wred[q][1]) + (wred[q][2] + wred[q][3]);
+      store3(gsum, k, r);
     }
     __syncthreads();
   }
@@ -262,8 +276,13 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
     return;
   }
   float G[kNP];
-#pragma unroll
-  for (int q = 0; q < kNP; ++q) G[q] = gsum[q * n + k];
+  {
+    const float4* Gp = (const float4*)gsum + k * 3;
+    const float4 a = Gp[0], b = Gp[1], c = Gp[2];
+    G[0] = a.x; G[1] = a.y; G[2] = a.z; G[3] = a.w;
+    G[4] = b.x; G[5] = b.y; G[6] = b.z; G[7] = b.w;
+    G[8] = c.x;
+  }
   const float gux = G[0], guy = G[1], gA11 = G[2], gA12 = G[3], gA22 = G[4];
   g_opacity[k] = G[5];
   // ---- colour -> SH coefficients and view direction
@@ -372,22 +391,27 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-void launch_backward(const BwdArgs& a, hipStream_t st) {
-  const int64_t n = a.s.n;
+void launch_backward_blend(const BwdArgs& a, hipStream_t st) {
   const int ntile = a.v.Tx * a.v.Ty;
   const int nblk = (ntile + 7) / 8 * 8;
   if (a.n_inst > 0) {
-    const int64_t m = (int64_t)kNP * a.n_inst;
-    hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(m)), dim3(kBlock), 0, st, a.partial, m);
+    const int64_t m = 3 * a.n_inst;
+    hipLaunchKernelGGL(k_fill_f4, dim3(grid_for(m)), dim3(kBlock), 0, st, (float4*)a.partial, m);
     hipLaunchKernelGGL(k_blend_bwd, dim3(nblk), dim3(kBlock), 0, st, a.ranges, a.tvals, a.rec,
                        a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last, a.dL_drgb, a.partial,
                        a.n_inst);
   }
+}
+
+void launch_backward_chain(const BwdArgs& a, hipStream_t st) {
+  const int64_t n = a.s.n;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_seg_small, dim3(grid_for(n)), dim3(kBlock), 0, st, a.count, a.emit_base,
-                     a.partial, a.n_inst, n, a.gsum, a.big, a.nbig);
-  hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, a.partial,
-                     a.n_inst, n, a.gsum, a.big, a.nbig);
+  if (a.n_vis > 0) {
+    hipLaunchKernelGGL(k_seg_small, dim3(grid_for(a.n_vis)), dim3(kBlock), 0, st, a.order, a.n_vis,
+                       a.count, a.emit_base, a.partial, a.gsum, a.big, a.nbig);
+    hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, a.partial,
+                       a.gsum, a.big, a.nbig);
+  }
   hipLaunchKernelGGL(k_chain, dim3(grid_for(n)), dim3(kBlock), 0, st, a.s, a.v, a.count, a.gsum,
                      a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh);
 }

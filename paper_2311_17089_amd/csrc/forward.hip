@@ -185,7 +185,8 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
                                                   const Rec* rec, ViewParams v, int ntile,
                                                   float* rgb, float* T_final, uint32_t* n_accum,
                                                   uint32_t* n_last,
-                                                  unsigned long long* blend_ctr) {
+                                                  unsigned long long* blend_ctr,
+                                                  unsigned long long* visit_ctr) {
   __shared__ float4 s0[kBlock], s1[kBlock], s2[kBlock];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntile) return;
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
   float T = 1.0f;
   float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
   uint32_t cnt = 0, last = 0;
+  uint32_t visits = inside ? rg.y - rg.x : 0u;  // replaced by the stop position on termination
   bool done = !inside;
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
     if (__syncthreads_count(!done) == 0) break;
@@ -228,6 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
         const float Tn = T * (1.0f - al);
         if (Tn < kTMin) {
           done = true;
+          visits = b0 - rg.x + (uint32_t)j + 1;
           break;
         }
         const float w = al * T;
@@ -251,10 +254,14 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
     n_last[pix] = last;
   }
   // per-workgroup blend count (wave reduction, one atomic per wave)
-  unsigned long long c64 = cnt;
+  unsigned long long c64 = cnt, v64 = visits;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) c64 += __shfl_xor(c64, o, 64);
+  for (int o = 32; o > 0; o >>= 1) {
+    c64 += __shfl_xor(c64, o, 64);
+    v64 += __shfl_xor(v64, o, 64);
+  }
   if (lane == 0 && c64) atomicAdd(blend_ctr, c64);
+  if (lane == 0 && v64) atomicAdd(visit_ctr, v64);
 }
 
 __global__ __launch_bounds__(kBlock) void k_debug_exp(const float* x, float* y, int64_t n) {
@@ -312,11 +319,11 @@ void launch_ranges(const uint32_t* tkeys, uint32_t ninst, uint2* ranges, hipStre
 
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* blend_ctr, hipStream_t st) {
+                  unsigned long long* blend_ctr, unsigned long long* visit_ctr, hipStream_t st) {
   const int ntile = v.Tx * v.Ty;
   const int nblk = (ntile + 7) / 8 * 8;
   hipLaunchKernelGGL(k_blend, dim3(nblk), dim3(kBlock), 0, st, ranges, tvals, rec, v, ntile, rgb,
-                     T_final, n_accum, n_last, blend_ctr);
+                     T_final, n_accum, n_last, blend_ctr, visit_ctr);
 }
 
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st) {

@@ -34,34 +34,6 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(MSGS_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-int ctx_alloc(msgs_context* c, void** p, size_t bytes, hipStream_t st) {
-  bytes = std::max<size_t>(bytes, 256);
-  if (c->budget) {
-    size_t cur = c->in_use.load();
-    do {
-      if (cur + bytes > c->budget)
-        return fail(MSGS_E_NOMEM, "context memory budget exceeded (" + std::to_string(cur + bytes) +
-                                      " > " + std::to_string(c->budget) + " bytes)");
-    } while (!c->in_use.compare_exchange_weak(cur, cur + bytes));
-  } else {
-    c->in_use += bytes;
-  }
-  hipError_t e = hipMallocAsync(p, bytes, st);
-  if (e != hipSuccess) {
-    c->in_use -= bytes;
-    (void)hipGetLastError();
-    return fail(MSGS_E_NOMEM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
-  }
-  return MSGS_OK;
-}
-
-void ctx_free(msgs_context* c, void* p, size_t bytes, hipStream_t st) {
-  if (!p) return;
-  bytes = std::max<size_t>(bytes, 256);
-  (void)hipFreeAsync(p, st);
-  c->in_use -= bytes;
-}
-
 // Small pinned host buffer per thread for count readbacks.
 unsigned long long* pinned_slot() {
   struct Slot {
@@ -116,23 +88,21 @@ int make_view(const msgs_camera* cam, const msgs_render_opts* o, int n_levels, V
 }
 
 void frame_free_all(msgs_frame* f) {
-  for (auto& b : f->bufs) ctx_free(f->ctx, b.first, b.second, f->st);
-  f->bufs.clear();
-}
-
-int frame_alloc(msgs_frame* f, void** p, size_t bytes) {
-  int rc = ctx_alloc(f->ctx, p, bytes, f->st);
-  if (rc == MSGS_OK) f->bufs.push_back({*p, std::max<size_t>(bytes, 256)});
-  return rc;
-}
-
-void frame_drop(msgs_frame* f, void* p) {
-  for (size_t i = 0; i < f->bufs.size(); ++i)
-    if (f->bufs[i].first == p) {
-      ctx_free(f->ctx, p, f->bufs[i].second, f->st);
-      f->bufs.erase(f->bufs.begin() + (long)i);
-      return;
+  for (void* b : f->blocks) f->ctx->cache.free(f->ctx, b, f->st);
+  f->blocks.clear();
+  if (f->tmp_block) {
+    f->ctx->cache.free(f->ctx, f->tmp_block, f->st);
+    f->tmp_block = nullptr;
+  }
+  for (auto& e : f->ev)
+    if (e) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
     }
+}
+
+void mark(msgs_frame* f, int i) {
+  if (f->profile && f->ev[i]) (void)hipEventRecord(f->ev[i], f->st);
 }
 
 int tile_bits(int ntile) {
@@ -140,6 +110,8 @@ int tile_bits(int ntile) {
   while (b < 32 && (1ll << b) < (long long)ntile) ++b;
   return b;
 }
+
+int radix_passes(int begin_bit, int end_bit) { return end_bit > begin_bit ? (end_bit - begin_bit + 7) / 8 : 0; }
 
 // Phase 1 of a render: projection, selection, compaction, depth sort, tile
 // counts.  Leaves the instance total in f->ctr[3] (device); no host sync.
@@ -150,45 +122,54 @@ int render_phase1(msgs_frame* f) {
   const int64_t P = (int64_t)v.W * v.H;
   const int ntile = v.Tx * v.Ty;
   const int64_t nb = (n + kBlock - 1) / kBlock;
-  int rc;
-#define ALLOC(ptr, bytes)                                            \
-  do {                                                               \
-    rc = frame_alloc(f, (void**)&(ptr), (size_t)(bytes));            \
-    if (rc != MSGS_OK) return rc;                                    \
-  } while (0)
-  ALLOC(f->ctr, 8 * sizeof(unsigned long long));
-  ALLOC(f->sel, n);
-  ALLOC(f->count, n * 4);
-  ALLOC(f->depthkey, n * 4);
-  ALLOC(f->rec, n * sizeof(Rec));
-  ALLOC(f->rect, n * sizeof(uint2));
-  ALLOC(f->emit_base, n * 4);
-  ALLOC(f->ranges, (size_t)ntile * sizeof(uint2));
-  ALLOC(f->T_final, P * 4);
-  ALLOC(f->n_accum, P * 4);
-  ALLOC(f->n_last, P * 4);
-  ALLOC(f->blk_vis, nb * 4);
-  ALLOC(f->blk_off, nb * 4);
-  ALLOC(f->dkeys[0], n * 4);
-  ALLOC(f->dvals[0], n * 4);
-  ALLOC(f->dkeys[1], n * 4);
-  ALLOC(f->dvals[1], n * 4);
-  ALLOC(f->cnt_d, n * 4);
-  ALLOC(f->off_d, n * 4);
-  ALLOC(f->scan_tmp, std::max(scan_tmp_bytes(n), scan_tmp_bytes(nb)));
-  ALLOC(f->sort_tmp, radix_tmp_bytes(n));
+  // the depth sort makes 4 passes and ends in its input buffers
+  const bool even = radix_passes(0, 32) % 2 == 0;
+  uint32_t* dv0 = nullptr;
+  Carve keep;
+  keep.add(&f->ctr, 8 * sizeof(unsigned long long));
+  keep.add(&f->sel, n);
+  keep.add(&f->count, n * 4);
+  keep.add(&f->depthkey, n * 4);
+  keep.add(&f->rec, n * sizeof(Rec));
+  keep.add(&f->rect, n * sizeof(uint2));
+  keep.add(&f->emit_base, n * 4);
+  keep.add(&f->ranges, (size_t)ntile * sizeof(uint2));
+  keep.add(&f->T_final, P * 4);
+  keep.add(&f->n_accum, P * 4);
+  keep.add(&f->n_last, P * 4);
+  keep.add(&f->order, n * 4);
+  keep.add(&f->off_d, n * 4);
+  Carve tmp;
+  tmp.add(&f->blk_vis, nb * 4);
+  tmp.add(&f->blk_off, nb * 4);
+  tmp.add(&f->dkeys[0], n * 4);
+  tmp.add(&f->dkeys[1], n * 4);
+  tmp.add(&f->dvals_alt, n * 4);
+  tmp.add(&f->cnt_d, n * 4);
+  tmp.add(&f->scan_tmp, std::max(scan_tmp_bytes(n), scan_tmp_bytes(nb)));
+  tmp.add(&f->sort_tmp, radix_tmp_bytes(n));
+  int rc = keep.alloc(f->ctx, st);
+  if (rc != MSGS_OK) return rc;
+  f->blocks.push_back(keep.base);
+  rc = tmp.alloc(f->ctx, st);
+  if (rc != MSGS_OK) return rc;
+  f->tmp_block = tmp.base;
+  uint32_t* vin = even ? f->order : f->dvals_alt;
+  uint32_t* valt = even ? f->dvals_alt : f->order;
+  dv0 = vin;
   launch_fill_u32((uint32_t*)f->ctr, 16, 0u, st);
+  mark(f, 0);
   launch_project(f->scene->view, v, f->sel, f->count, f->depthkey, f->rec, f->rect, f->blk_vis,
                  &f->ctr[0], st);
   scan_excl_u32(f->blk_vis, f->blk_off, nullptr, nb, &f->ctr[2], f->scan_tmp, st);
-  launch_compact(f->count, f->depthkey, n, f->blk_off, f->dkeys[0], f->dvals[0], st);
+  launch_compact(f->count, f->depthkey, n, f->blk_off, f->dkeys[0], dv0, st);
+  mark(f, 1);
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
-  int alt = radix_sort_pairs(f->dkeys[0], f->dvals[0], f->dkeys[1], f->dvals[1], d_nvis, n, 0, 32,
-                             f->sort_tmp, st);
-  f->vals_sorted = f->dvals[alt];
-  launch_gather_counts(f->vals_sorted, f->count, d_nvis, n, f->cnt_d, st);
+  radix_sort_pairs(f->dkeys[0], vin, f->dkeys[1], valt, d_nvis, n, 0, 32, f->sort_tmp, st);
+  mark(f, 2);
+  launch_gather_counts(f->order, f->count, d_nvis, n, f->cnt_d, st);
   scan_excl_u32(f->cnt_d, f->off_d, d_nvis, n, &f->ctr[3], f->scan_tmp, st);
-  (void)P;
+  mark(f, 3);
   return MSGS_OK;
 }
 
@@ -199,43 +180,48 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   hipStream_t st = f->st;
   const int ntile = v.Tx * v.Ty;
   const int64_t I = f->n_inst;
-  int rc;
-  uint32_t *tk0 = nullptr, *tv0 = nullptr, *tk1 = nullptr, *tv1 = nullptr;
-  void* tmp = nullptr;
-  ALLOC(tk0, I * 4);
-  ALLOC(tv0, I * 4);
-  ALLOC(tk1, I * 4);
-  ALLOC(tv1, I * 4);
-  ALLOC(tmp, radix_tmp_bytes(I));
+  const int bits = tile_bits(ntile);
+  const bool even = radix_passes(0, bits) % 2 == 0;
+  // the sorted list must end in the kept block: emit into it for an even
+  // number of passes, into the temporary block for an odd number
+  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
+  void* stmp = nullptr;
+  Carve keep, tmp;
+  keep.add(&ka, I * 4);
+  keep.add(&va, I * 4);
+  tmp.add(&kb, I * 4);
+  tmp.add(&vb, I * 4);
+  tmp.add(&stmp, radix_tmp_bytes(I));
+  int rc = keep.alloc(f->ctx, st);
+  if (rc != MSGS_OK) return rc;
+  f->blocks.push_back(keep.base);
+  rc = tmp.alloc(f->ctx, st);
+  if (rc != MSGS_OK) return rc;
+  uint32_t* k0 = even ? ka : kb;
+  uint32_t* v0 = even ? va : vb;
+  uint32_t* k1 = even ? kb : ka;
+  uint32_t* v1 = even ? vb : va;
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
-  launch_emit(f->vals_sorted, f->off_d, d_nvis, n, f->rect, v.Tx, tk0, tv0, f->emit_base, st);
-  int alt = radix_sort_pairs(tk0, tv0, tk1, tv1, nullptr, I, 0, tile_bits(ntile), tmp, st);
-  f->tkeys = alt ? tk1 : tk0;
-  f->tvals = alt ? tv1 : tv0;
-  frame_drop(f, alt ? tk0 : tk1);
-  frame_drop(f, alt ? tv0 : tv1);
-  frame_drop(f, tmp);
+  mark(f, 4);
+  launch_emit(f->order, f->off_d, d_nvis, n, f->rect, v.Tx, k0, v0, f->emit_base, st);
+  mark(f, 5);
+  radix_sort_pairs(k0, v0, k1, v1, nullptr, I, 0, bits, stmp, st);
+  mark(f, 6);
+  f->tkeys = ka;
+  f->tvals = va;
   launch_fill_u32((uint32_t*)f->ranges, (int64_t)ntile * 2, 0u, st);
   launch_ranges(f->tkeys, (uint32_t)I, f->ranges, st);
+  mark(f, 7);
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
-               &f->ctr[1], st);
-  // temporaries of phase 1 are no longer needed
-  frame_drop(f, f->blk_vis);
-  frame_drop(f, f->blk_off);
-  frame_drop(f, f->dkeys[0]);
-  frame_drop(f, f->dkeys[1]);
-  frame_drop(f, f->dvals[0]);
-  frame_drop(f, f->dvals[1]);
-  frame_drop(f, f->cnt_d);
-  frame_drop(f, f->off_d);
-  frame_drop(f, f->scan_tmp);
-  frame_drop(f, f->sort_tmp);
-  f->blk_vis = f->blk_off = f->cnt_d = f->off_d = nullptr;
-  f->dkeys[0] = f->dkeys[1] = f->dvals[0] = f->dvals[1] = nullptr;
-  f->vals_sorted = nullptr;
+               &f->ctr[1], &f->ctr[4], st);
+  mark(f, 8);
+  f->ctx->cache.free(f->ctx, tmp.base, st);
+  f->ctx->cache.free(f->ctx, f->tmp_block, st);
+  f->tmp_block = nullptr;
+  f->blk_vis = f->blk_off = f->cnt_d = f->dvals_alt = nullptr;
+  f->dkeys[0] = f->dkeys[1] = nullptr;
   f->scan_tmp = f->sort_tmp = nullptr;
   return MSGS_OK;
-#undef ALLOC
 }
 
 }  // namespace msgs
@@ -255,6 +241,7 @@ void msgs_default_opts(msgs_render_opts* o) {
   o->lowpass = 0.3f;
   o->near_z = 0.2f;
   o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
+  o->profile = 0;
 }
 
 int msgs_context_create(int device, size_t pool_bytes, msgs_context** out) {
@@ -414,6 +401,17 @@ int msgs_render(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
   f->v = v;
   f->opts = o;
   f->n = s->view.n;
+  f->profile = o.profile != 0;
+  if (f->profile) {
+    for (auto& ev : f->ev) {
+      e = hipEventCreate(&ev);
+      if (e != hipSuccess) {
+        frame_free_all(f);
+        delete f;
+        return hip_fail(e, "hipEventCreate");
+      }
+    }
+  }
   rc = render_phase1(f);
   if (rc == MSGS_OK) {
     unsigned long long* hp = pinned_slot();
@@ -457,16 +455,6 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  struct Tmp {
-    void* p;
-    size_t b;
-  };
-  std::vector<Tmp> tmp;
-  auto alloc = [&](void** p, size_t bytes) {
-    int rc = ctx_alloc(c, p, bytes, st);
-    if (rc == MSGS_OK) tmp.push_back({*p, std::max<size_t>(bytes, 256)});
-    return rc;
-  };
   BwdArgs a{};
   a.s = f->scene->view;
   a.v = f->v;
@@ -476,6 +464,8 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   a.rect = f->rect;
   a.emit_base = f->emit_base;
   a.count = f->count;
+  a.order = f->order;
+  a.n_vis = f->n_vis;
   a.T_final = f->T_final;
   a.n_last = f->n_last;
   a.dL_drgb = dL_drgb;
@@ -485,17 +475,27 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   a.g_quats = out->quats;
   a.g_opacity = out->opacity;
   a.g_sh = out->sh;
-  int rc = alloc((void**)&a.partial, (size_t)9 * 4 * (size_t)f->n_inst);
-  if (rc == MSGS_OK) rc = alloc((void**)&a.gsum, (size_t)9 * 4 * (size_t)n);
-  if (rc == MSGS_OK) rc = alloc((void**)&a.big, (size_t)4 * (size_t)n);
-  if (rc == MSGS_OK) rc = alloc((void**)&a.nbig, 4);
+  Carve tmp;
+  tmp.add(&a.partial, (size_t)48 * (size_t)f->n_inst);
+  tmp.add(&a.gsum, (size_t)48 * (size_t)n);
+  tmp.add(&a.big, (size_t)4 * (size_t)n);
+  tmp.add(&a.nbig, 4);
+  int rc = tmp.alloc(c, st);
   if (rc == MSGS_OK) {
     launch_fill_u32(a.nbig, 1, 0u, st);
-    launch_backward(a, st);
+    msgs_frame* fm = const_cast<msgs_frame*>(f);
+    if (fm->profile) (void)hipEventRecord(fm->ev[9], st);
+    launch_backward_blend(a, st);
+    if (fm->profile) (void)hipEventRecord(fm->ev[10], st);
+    launch_backward_chain(a, st);
+    if (fm->profile) {
+      (void)hipEventRecord(fm->ev[11], st);
+      fm->bwd_recorded = true;
+    }
     e = hipGetLastError();
     if (e != hipSuccess) rc = hip_fail(e, "backward launch");
+    c->cache.free(c, tmp.base, st);
   }
-  for (auto& t : tmp) ctx_free(c, t.p, t.b, st);
   return rc;
 }
 
@@ -518,9 +518,34 @@ int msgs_frame_stats(const msgs_frame* f, msgs_stats* out) {
   if (!f || !out) return fail(MSGS_E_INVALID, "null argument");
   int rc = frame_sync(f);
   if (rc != MSGS_OK) return rc;
-  unsigned long long h[4];
+  unsigned long long h[5];
   hipError_t e = hipMemcpy(h, f->ctr, sizeof h, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "stats readback");
+  for (int i = 0; i < 10; ++i) out->stage_us[i] = 0.0f;
+  if (f->profile) {
+    auto span = [&](int a, int b) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, f->ev[a], f->ev[b]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.0f;
+      }
+      return ms * 1000.0f;
+    };
+    out->stage_us[0] = span(0, 1);
+    out->stage_us[1] = span(1, 2);
+    out->stage_us[2] = span(2, 3);
+    out->stage_us[3] = span(4, 5);
+    out->stage_us[4] = span(5, 6);
+    out->stage_us[5] = span(6, 7);
+    out->stage_us[6] = span(7, 8);
+    out->stage_us[9] = span(0, 3) + span(4, 8);
+    if (f->bwd_recorded) {
+      (void)hipEventSynchronize(f->ev[11]);
+      out->stage_us[7] = span(9, 10);
+      out->stage_us[8] = span(10, 11);
+    }
+  }
+  out->n_visits = (int64_t)h[4];
   out->n_gaussians = f->n;
   out->n_selected = (int64_t)h[0];
   out->n_visible = (int64_t)h[2];

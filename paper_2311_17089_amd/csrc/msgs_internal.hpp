@@ -11,10 +11,41 @@
 #include "../../include/msgs.h"
 #include "msgs_device.hpp"
 
+namespace msgs {
+// Stream-ordered caching allocator (alloc.cpp).
+class DeviceCache {
+ public:
+  DeviceCache();
+  ~DeviceCache();
+  int alloc(msgs_context* c, void** out, size_t bytes, hipStream_t st);
+  void free(msgs_context* c, void* p, hipStream_t st);
+  void release_idle();
+  size_t idle_bytes();
+
+ private:
+  struct Impl;
+  Impl* impl;
+};
+
+// Several buffers carved out of one allocation (256-byte aligned parts).
+struct Carve {
+  std::vector<std::pair<void**, size_t>> parts;
+  size_t total = 0;
+  void* base = nullptr;
+  template <typename T>
+  void add(T** slot, size_t bytes) {
+    add((void**)slot, bytes);
+  }
+  size_t add(void** slot, size_t bytes);
+  int alloc(msgs_context* c, hipStream_t st);
+};
+}  // namespace msgs
+
 struct msgs_context {
   int device = 0;
   size_t budget = 0;                 // 0 = unlimited
   std::atomic<size_t> in_use{0};     // bytes held by scenes and frames
+  msgs::DeviceCache cache;
 };
 
 struct msgs_scene {
@@ -33,9 +64,13 @@ struct msgs_frame {
   int64_t n = 0;
   int64_t n_vis = 0;
   int64_t n_inst = 0;
-  std::vector<std::pair<void*, size_t>> bufs;
+  std::vector<void*> blocks;          // allocations owned by the frame
+  // profiling events (opts.profile): forward stage boundaries 0..8, backward 9..11
+  bool profile = false;
+  hipEvent_t ev[12] = {};
+  bool bwd_recorded = false;
   // kept for the backward pass and the getters
-  unsigned long long* ctr = nullptr;   // [0] selected, [1] blends, [2] visible, [3] instances
+  unsigned long long* ctr = nullptr;   // [0] selected [1] blends [2] visible [3] instances [4] visits
   uint8_t* sel = nullptr;
   uint32_t* count = nullptr;
   uint32_t* depthkey = nullptr;
@@ -48,14 +83,15 @@ struct msgs_frame {
   uint32_t* n_last = nullptr;
   uint32_t* tkeys = nullptr;
   uint32_t* tvals = nullptr;
-  // temporaries of the render
+  uint32_t* order = nullptr;          // drawable Gaussians in depth order
+  uint32_t* off_d = nullptr;          // their emission offsets
+  // temporaries of the render (one block, released after blending)
+  void* tmp_block = nullptr;
   uint32_t* blk_vis = nullptr;
   uint32_t* blk_off = nullptr;
   uint32_t* dkeys[2] = {nullptr, nullptr};
-  uint32_t* dvals[2] = {nullptr, nullptr};
-  uint32_t* vals_sorted = nullptr;
+  uint32_t* dvals_alt = nullptr;
   uint32_t* cnt_d = nullptr;
-  uint32_t* off_d = nullptr;
   void* scan_tmp = nullptr;
   void* sort_tmp = nullptr;
 };
@@ -64,8 +100,7 @@ namespace msgs {
 extern thread_local std::string t_err;
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
-int ctx_alloc(msgs_context* c, void** p, size_t bytes, hipStream_t st);
-void ctx_free(msgs_context* c, void* p, size_t bytes, hipStream_t st);
+
 int make_view(const msgs_camera* cam, const msgs_render_opts* o, int n_levels, ViewParams* v);
 int render_phase1(msgs_frame* f);
 int render_phase2(msgs_frame* f, float* rgb_out);

@@ -24,7 +24,7 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 void launch_ranges(const uint32_t* tkeys, uint32_t ninst, uint2* ranges, hipStream_t st);
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* blend_ctr, hipStream_t st);
+                  unsigned long long* blend_ctr, unsigned long long* visit_ctr, hipStream_t st);
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st);
 void launch_debug_log(const float* x, float* y, int64_t n, hipStream_t st);
 
@@ -51,12 +51,14 @@ struct BwdArgs {
   const uint2* rect;
   const uint32_t* emit_base;
   const uint32_t* count;
+  const uint32_t* order;    // drawable Gaussians in depth (emission) order
+  int64_t n_vis;
   const float* T_final;
   const uint32_t* n_last;
   const float* dL_drgb;
-  float* partial;           // [9][n_inst] per-instance partials
+  float* partial;           // [n_inst][12] per-instance partials (9 used)
   int64_t n_inst;
-  float* gsum;              // [9][n] per-Gaussian sums
+  float* gsum;              // [n][12] per-Gaussian sums (9 used)
   uint32_t* big;            // [n] Gaussians with many tiles
   uint32_t* nbig;           // device counter, zeroed by the caller
   float* g_means;
@@ -65,6 +67,7 @@ struct BwdArgs {
   float* g_opacity;
   float* g_sh;
 };
-void launch_backward(const BwdArgs& a, hipStream_t st);
+void launch_backward_blend(const BwdArgs& a, hipStream_t st);
+void launch_backward_chain(const BwdArgs& a, hipStream_t st);
 
 }  // namespace msgs
