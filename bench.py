@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
+    ap.add_argument("--serial", action="store_true",
+                    help="render the frames of a step one after another on one stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path runs on a single MI355X and this build "
@@ -152,12 +154,28 @@ def main():
         g = torch.Generator().manual_seed(500 + i)
         dls[ds] = torch.randn((H_FULL // ds, W_FULL // ds, 3), generator=g).cuda() * 1e-3
     stream = torch.cuda.current_stream()
+    # one stream and one host thread per frame: the four frames of a step are
+    # independent, so the small ones run on the CUs the 1x frame leaves idle
+    from concurrent.futures import ThreadPoolExecutor
+    streams = {ds: torch.cuda.Stream() for ds in DOWNSCALES}
+    pool = ThreadPoolExecutor(max_workers=len(DOWNSCALES))
+
+    def frame(ds):
+        st = streams[ds]
+        with torch.cuda.stream(st):
+            _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, stream=st)
+            M.render_backward(ctx, fr, dls[ds], stream=st)
+            fr.release()
 
     def step():
-        for ds in DOWNSCALES:
-            _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True)
-            M.render_backward(ctx, fr, dls[ds])
-            fr.release()
+        if args.serial:
+            for ds in DOWNSCALES:
+                _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True)
+                M.render_backward(ctx, fr, dls[ds])
+                fr.release()
+            return
+        for f in [pool.submit(frame, ds) for ds in DOWNSCALES]:
+            f.result()
 
     # counts of one step (deterministic)
     stats = {}
@@ -179,6 +197,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt / args.steps * 1e3
+    pool.shutdown()
 
     # live per-stage device time over the timed configuration (profiled steps)
     prof_steps = max(3, min(args.steps, 10))
@@ -261,6 +280,7 @@ def main():
                                "1600x1064 at 1x/4x/16x/64x, selective rendering, forward + backward "
                                "per downscale",
                    "n_gaussians": sc.n, "frames_per_step": len(DOWNSCALES),
+                   "frames_in_flight": 1 if args.serial else len(DOWNSCALES),
                    "blends_per_step": blends_per_step},
         "roofline": roof,
         "stage_us_per_step": {s: round(v, 2) for s, v in stage_tot.items()},

@@ -121,7 +121,10 @@ typedef struct {
   int64_t n_visible;    /* selected with at least one tile */
   int64_t n_instances;  /* (Gaussian, tile) pairs */
   int64_t n_blends;     /* accumulated contributions over all pixels */
-  int64_t n_visits;     /* (pixel, instance) pairs the blend kernel evaluated */
+  int64_t n_visits;     /* (pixel, instance) pairs up to each pixel's stop position in
+                           its tile list (the work of plain tile compositing) */
+  int64_t n_evals;      /* (pixel, instance) pairs whose Gaussian was evaluated after
+                           the per-quadrant footprint cull */
   int width, height, tiles_x, tiles_y;
   /* device time (us) per stage when rendered with profile = 1, else 0:
    * [0] projection + selection + compaction  [1] depth sort  [2] tile-count scan

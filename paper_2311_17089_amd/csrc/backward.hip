@@ -44,8 +44,9 @@ __device__ __forceinline__ float wave_sum_to_63(float v) {
 }
 
 __device__ __forceinline__ int xcd_tile_b(int b, int nblk) {
-  const int per = nblk >> 3;
-  return (b & 7) * per + (b >> 3);
+  (void)nblk;
+  const int c = b >> 3;  // index of the workgroup within its XCD
+  return (((c >> 2) << 3) + (b & 7)) * 4 + (c & 3);
 }
 
 __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const uint32_t* tvals,
@@ -53,17 +54,20 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
                                                       const uint32_t* emit_base, ViewParams v,
                                                       int ntile, const float* T_final,
                                                       const uint32_t* n_last, const float* dLdC,
-                                                      float* partial, int64_t ninst) {
+                                                      float* partial) {
   __shared__ float4 s0[kBB], s1[kBB], s2[kBB];
-  __shared__ uint32_t sslot[kBB];
   __shared__ float red[kNP][kBlock / 64][kBB];
+  __shared__ uint8_t lists[4][256];
+  __shared__ uint32_t len[4];
+  __shared__ uint32_t wcnt[4][4];
   __shared__ uint32_t smax[kBlock / 64];
   const int tile = xcd_tile_b(blockIdx.x, gridDim.x);
   if (tile >= ntile) return;
   const int tx = tile % v.Tx, ty = tile / v.Tx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const int x0 = tx * kTile, y0 = ty * kTile;
+  const int px = x0 + (wave & 1) * 8 + (lane & 7);
+  const int py = y0 + (wave >> 1) * 8 + (lane >> 3);
   const bool inside = px < v.W && py < v.H;
   const float pcx = (float)px + 0.5f;
   const float pcy = (float)py + 0.5f;
@@ -88,24 +92,41 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
   uint32_t maxlast = 0;
 #pragma unroll
   for (int w = 0; w < kBlock / 64; ++w) maxlast = max(maxlast, smax[w]);
-  const int tw = (int)(v.Tx);
-  for (uint32_t hi = rg.x + maxlast; hi > rg.x;) {
+  // batches walk the list back to front (thread t holds position hi - 1 - t);
+  // the gathers of the next batch are in flight while one is replayed
+  float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
+  uint32_t nslot = 0;
+  auto fetch = [&](uint32_t hi) {
+    const uint32_t k = tvals[hi - 1 - threadIdx.x];
+    const Rec* rp = rec + k;
+    n0 = rp->r0;
+    n1 = rp->r1;
+    n2 = rp->r2;
+    const uint2 rr = rect[k];
+    const int xl = rr.x & 0xffff, xh = rr.x >> 16, yl = rr.y & 0xffff;
+    nslot = emit_base[k] + (uint32_t)((ty - yl) * (xh - xl + 1) + (tx - xl));
+  };
+  const uint32_t top = rg.x + maxlast;
+  bool have = top > rg.x && threadIdx.x < min((uint32_t)kBB, maxlast);
+  if (have) fetch(top);
+  for (uint32_t hi = top; hi > rg.x;) {
     const uint32_t lo = hi - rg.x > (uint32_t)kBB ? hi - kBB : rg.x;
     const int nb = (int)(hi - lo);
-    __syncthreads();
-    if ((int)threadIdx.x < nb) {
-      const uint32_t idx = hi - 1 - threadIdx.x;
-      const uint32_t k = tvals[idx];
-      const Rec r = rec[k];
-      s0[threadIdx.x] = r.r0;
-      s1[threadIdx.x] = r.r1;
-      s2[threadIdx.x] = r.r2;
-      const uint2 rr = rect[k];
-      const int xl = rr.x & 0xffff, xh = rr.x >> 16, yl = rr.y & 0xffff;
-      sslot[threadIdx.x] = emit_base[k] + (uint32_t)((ty - yl) * (xh - xl + 1) + (tx - xl));
+    uint32_t qm = 0;
+    const uint32_t slot = nslot;
+    if (have) {
+      s0[threadIdx.x] = n0;
+      s1[threadIdx.x] = n1;
+      s2[threadIdx.x] = n2;
+      qm = quad_mask(n0.x, n0.y, n2.z, n2.w, x0, y0);
     }
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
+    build_wave_lists(qm, have, lists, len, wcnt);
+    const uint32_t nlo = lo - rg.x > (uint32_t)kBB ? lo - kBB : rg.x;
+    have = lo > rg.x && (int)threadIdx.x < (int)(lo - nlo);
+    if (have) fetch(lo);
+    const int nl = (int)len[wave];
+    for (int i = 0; i < nl; ++i) {
+      const int j = lists[wave][i];
       const uint32_t pos = hi - 1 - (uint32_t)j - rg.x;  // position in the tile list
       float g[kNP];
       bool contrib = false;
@@ -114,8 +135,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
         const float4 b = s1[j];
         const float dx = pcx - a.x;
         const float dy = pcy - a.y;
-        const float qx = dx * dx, qy = dy * dy, qxy = dx * dy;
-        const float e = -0.5f * (a.z * qx + b.x * qy);
+        const float qxx = dx * dx, qyy = dy * dy, qxy = dx * dy;
+        const float e = -0.5f * (a.z * qxx + b.x * qyy);
         const float power = e - a.w * qxy;
         if (!(power > 0.0f || power < b.z)) {
           const float ex = exp_c(power);
@@ -140,9 +161,9 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
             const float dar = ar > kAlphaMax ? 0.0f : dal;
             g[5] = dar * ex;
             const float dp = dar * ar;
-            g[2] = dp * (-0.5f * qx);
+            g[2] = dp * (-0.5f * qxx);
             g[3] = dp * (-qxy);
-            g[4] = dp * (-0.5f * qy);
+            g[4] = dp * (-0.5f * qyy);
             g[0] = dp * (a.z * dx + a.w * dy);
             g[1] = dp * (b.x * dy + a.w * dx);
           }
@@ -151,8 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       if (__ballot(contrib)) {
 #pragma unroll
         for (int q = 0; q < kNP; ++q) {
-          const float s = wave_sum_to_63(contrib ? g[q] : 0.0f);
-          if (lane == 63) red[q][wave][j] = s;
+          const float sm = wave_sum_to_63(contrib ? g[q] : 0.0f);
+          if (lane == 63) red[q][wave][j] = sm;
         }
       } else if (lane == 0) {
 #pragma unroll
@@ -160,25 +181,28 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       }
     }
     __syncthreads();
-    if ((int)threadIdx.x < nb) {
-      float s[kNP];
+    if ((int)threadIdx.x < nb && qm) {
+      float sm[kNP];
       bool any = false;
 #pragma unroll
       for (int q = 0; q < kNP; ++q) {
-        s[q] = (red[q][0][threadIdx.x] + red[q][1][threadIdx.x]) +
-               (red[q][2][threadIdx.x] + red[q][3][threadIdx.x]);
-        any = any || s[q] != 0.0f;
+        float r = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w)
+          if ((qm >> w) & 1u) r += red[q][w][threadIdx.x];
+        sm[q] = r;
+        any = any || r != 0.0f;
       }
       if (any) {
-        float4* P = (float4*)partial + (int64_t)sslot[threadIdx.x] * 3;
-        P[0] = make_float4(s[0], s[1], s[2], s[3]);
-        P[1] = make_float4(s[4], s[5], s[6], s[7]);
-        P[2] = make_float4(s[8], 0.0f, 0.0f, 0.0f);
+        float4* P = (float4*)partial + (int64_t)slot * 3;
+        P[0] = make_float4(sm[0], sm[1], sm[2], sm[3]);
+        P[1] = make_float4(sm[4], sm[5], sm[6], sm[7]);
+        P[2] = make_float4(sm[8], 0.0f, 0.0f, 0.0f);
       }
     }
+    __syncthreads();
     hi = lo;
   }
-  (void)tw;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_f4(float4* p, int64_t n) {
@@ -255,7 +279,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
   }
 }
 
-// Chain rule per Gaussian.
+// Chain rule per Gaussian (SH degree D as a template parameter so that the
+// coefficient loads are issued together).
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, const uint32_t* count,
                                                   const float* gsum, float* g_means,
                                                   float* g_scales, float* g_quats,
@@ -263,8 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
   const int64_t n = s.n;
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
-  const int D = s.sh_degree;
-  const int K = (D + 1) * (D + 1);
+  constexpr int K = (D + 1) * (D + 1);
   Geo g;
   bool live = count[k] > 0 && project_geo(s, v, k, g);
   if (!live) {
@@ -272,6 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
     for (int i = 0; i < 3; ++i) g_scales[i * n + k] = 0.0f;
     for (int i = 0; i < 4; ++i) g_quats[i * n + k] = 0.0f;
     g_opacity[k] = 0.0f;
+#pragma unroll
     for (int j = 0; j < K * 3; ++j) g_sh[(int64_t)j * n + k] = 0.0f;
     return;
   }
@@ -293,17 +319,22 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
   float Y[16], Yx[16], Yy[16], Yz[16];
   sh_eval(D, x, y, z, Y);
   sh_grad(D, x, y, z, Yx, Yy, Yz);
+  float f[K * 3];
+#pragma unroll
+  for (int j = 0; j < K * 3; ++j) f[j] = s.sh[(int64_t)j * n + k];
   float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
     float acc = 0.5f;
-    for (int j = 0; j < K; ++j) acc = acc + Y[j] * s.sh[(int64_t)(j * 3 + c) * n + k];
+#pragma unroll
+    for (int j = 0; j < K; ++j) acc = acc + Y[j] * f[j * 3 + c];
     const float gc = acc < 0.0f ? 0.0f : G[6 + c];
+#pragma unroll
     for (int j = 0; j < K; ++j) {
-      const float f = s.sh[(int64_t)(j * 3 + c) * n + k];
       g_sh[(int64_t)(j * 3 + c) * n + k] = Y[j] * gc;
-      gdx += gc * f * Yx[j];
-      gdy += gc * f * Yy[j];
-      gdz += gc * f * Yz[j];
+      gdx += gc * f[j * 3 + c] * Yx[j];
+      gdy += gc * f[j * 3 + c] * Yy[j];
+      gdz += gc * f[j * 3 + c] * Yz[j];
     }
   }
   // unit direction d = v / |v|: dL/dv = (g - d (d . g)) / |v|
@@ -393,13 +424,12 @@ static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) 
 
 void launch_backward_blend(const BwdArgs& a, hipStream_t st) {
   const int ntile = a.v.Tx * a.v.Ty;
-  const int nblk = (ntile + 7) / 8 * 8;
+  const int nblk = (ntile + 31) / 32 * 32;
   if (a.n_inst > 0) {
     const int64_t m = 3 * a.n_inst;
     hipLaunchKernelGGL(k_fill_f4, dim3(grid_for(m)), dim3(kBlock), 0, st, (float4*)a.partial, m);
     hipLaunchKernelGGL(k_blend_bwd, dim3(nblk), dim3(kBlock), 0, st, a.ranges, a.tvals, a.rec,
-                       a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last, a.dL_drgb, a.partial,
-                       a.n_inst);
+                       a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last, a.dL_drgb, a.partial);
   }
 }
 
@@ -412,8 +442,13 @@ void launch_backward_chain(const BwdArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, a.partial,
                        a.gsum, a.big, a.nbig);
   }
-  hipLaunchKernelGGL(k_chain, dim3(grid_for(n)), dim3(kBlock), 0, st, a.s, a.v, a.count, a.gsum,
-                     a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh);
+  const dim3 g(grid_for(n)), b(kBlock);
+  switch (a.s.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_chain<0>, g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh); break;
+    case 1: hipLaunchKernelGGL(k_chain<1>, g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh); break;
+    case 2: hipLaunchKernelGGL(k_chain<2>, g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh); break;
+    default: hipLaunchKernelGGL(k_chain<3>, g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh); break;
+  }
 }
 
 }  // namespace msgs

@@ -8,17 +8,21 @@
 //              Gaussians feed the order-preserving compaction.
 //  k_compact   order-preserving compaction of drawable Gaussians into
 //              (depth key, index) pairs (wave ballot + block prefix).
-//  k_gather_counts / k_emit   tile counts in depth order, then one instance
-//              (tile, Gaussian) per tile of each rectangle, row-major.
+//  k_emit      one instance (tile, Gaussian) per tile of each rectangle,
+//              row-major, Gaussians in depth order (load-balanced per wave).
 //  k_ranges    half-open range of every tile in the tile-sorted list.
-//  k_blend     one 256-thread workgroup per 16x16 tile; records staged in LDS
-//              in batches of 256, every wave64 owns an 8x8 quadrant, front-to-
-//              back compositing with early exit; XCD-aware tile order.
+//  k_blend     one 256-thread workgroup per 16x16 tile whose four wave64s
+//              work independently on their 8x8 quadrants: per 64-instance chunk
+//              a ballot keeps the instances whose level-set box reaches the
+//              quadrant, packed in order into the wave's LDS buffer; branch-free
+//              front-to-back compositing with per-wave early exit; the next
+//              chunk's gathers in flight meanwhile; XCD-aware tile order.
 #include "msgs_device.hpp"
 #include "msgs_kernels.hpp"
 
 namespace msgs {
 
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, uint8_t* sel_out,
                                                     uint32_t* count, uint32_t* depthkey,
                                                     Rec* rec, uint2* rect, uint32_t* blk_vis,
@@ -79,21 +83,24 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, u
           d0 = d0 / dn;
           d1 = d1 / dn;
           d2 = d2 / dn;
+          constexpr int K = (D + 1) * (D + 1);
+          float f[K * 3];
+#pragma unroll
+          for (int j = 0; j < K * 3; ++j) f[j] = s.sh[(int64_t)j * n + k];
           float Y[16];
-          const int D = s.sh_degree;
           sh_eval(D, d0, d1, d2, Y);
-          const int K = (D + 1) * (D + 1);
           float col[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             float acc = 0.5f;
-            for (int j = 0; j < K; ++j) acc = acc + Y[j] * s.sh[(int64_t)(j * 3 + c) * n + k];
+#pragma unroll
+            for (int j = 0; j < K; ++j) acc = acc + Y[j] * f[j * 3 + c];
             col[c] = fmaxf(acc, 0.0f);
           }
           Rec r;
           r.r0 = make_float4(g.ux, g.uy, A11, A12);
           r.r1 = make_float4(A22, sig, -lq, col[0]);
-          r.r2 = make_float4(col[1], col[2], g.p[2], 0.0f);
+          r.r2 = make_float4(col[1], col[2], ex, ey);
           rec[k] = r;
           rect[k] = make_uint2((uint32_t)xl | ((uint32_t)xh << 16), (uint32_t)yl | ((uint32_t)yh << 16));
           depthkey[k] = __float_as_uint(g.p[2]);
@@ -129,32 +136,53 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* count, const
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_gather_counts(const uint32_t* vals_sorted,
-                                                          const uint32_t* count,
-                                                          const uint32_t* d_nvis, int64_t nmax,
-                                                          uint32_t* out) {
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= nmax) return;
-  out[j] = (j < (int64_t)*d_nvis) ? count[vals_sorted[j]] : 0u;
-}
+constexpr uint32_t kEmitSmall = 16;
 
-__global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* vals_sorted, const uint32_t* off,
-                                                 const uint32_t* d_nvis, const uint2* rect,
-                                                 int Tx, uint32_t* tkeys, uint32_t* tvals,
-                                                 uint32_t* emit_base) {
+// One (tile, Gaussian) instance per tile of every drawable Gaussian, in depth
+// order, tiles of a rectangle row-major.  A Gaussian with at most kEmitSmall
+// tiles is written by its own thread; larger ones are written by the whole
+// wave, 64 consecutive instances at a time.
+__global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* order, const uint32_t* off,
+                                                 const uint32_t* d_nvis, const uint32_t* count,
+                                                 const uint2* rect, int Tx, uint32_t* tkeys,
+                                                 uint32_t* tvals, uint32_t* emit_base) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= (int64_t)*d_nvis) return;
-  const uint32_t k = vals_sorted[j];
-  uint32_t i = off[j];
-  emit_base[k] = i;
-  const uint2 r = rect[k];
-  const int xl = r.x & 0xffff, xh = r.x >> 16, yl = r.y & 0xffff, yh = r.y >> 16;
-  for (int ty = yl; ty <= yh; ++ty) {
-    const uint32_t row = (uint32_t)ty * (uint32_t)Tx;
-    for (int tx = xl; tx <= xh; ++tx) {
-      tkeys[i] = row + (uint32_t)tx;
-      tvals[i] = k;
-      ++i;
+  const int lane = threadIdx.x & 63;
+  const bool valid = j < (int64_t)*d_nvis;
+  uint32_t k = 0, base = 0, c = 0;
+  uint2 r = make_uint2(0u, 0u);
+  if (valid) {
+    k = order[j];
+    base = off[j];
+    c = count[k];
+    r = rect[k];
+    emit_base[k] = base;
+  }
+  const bool big = valid && c > kEmitSmall;
+  if (valid && !big) {
+    const int xl = r.x & 0xffff, xh = r.x >> 16, yl = r.y & 0xffff, yh = r.y >> 16;
+    uint32_t i = base;
+    for (int ty = yl; ty <= yh; ++ty) {
+      const uint32_t row = (uint32_t)ty * (uint32_t)Tx;
+      for (int tx = xl; tx <= xh; ++tx) {
+        tkeys[i] = row + (uint32_t)tx;
+        tvals[i] = k;
+        ++i;
+      }
+    }
+  }
+  unsigned long long m = __ballot(big);
+  while (m) {
+    const int src = __ffsll((long long)m) - 1;
+    m &= m - 1;
+    const uint32_t bk = __shfl(k, src, 64), bb = __shfl(base, src, 64), bc = __shfl(c, src, 64);
+    const uint32_t rx = __shfl(r.x, src, 64), ry = __shfl(r.y, src, 64);
+    const uint32_t xl = rx & 0xffff, xh = rx >> 16, yl = ry & 0xffff;
+    const uint32_t nx = xh - xl + 1;
+    for (uint32_t li = lane; li < bc; li += 64) {
+      const uint32_t dy = li / nx, dx = li - dy * nx;
+      tkeys[bb + li] = (yl + dy) * (uint32_t)Tx + xl + dx;
+      tvals[bb + li] = bk;
     }
   }
 }
@@ -174,74 +202,125 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* tkeys, uint32
 }
 
 // Tile for a workgroup: workgroups are dispatched round-robin over the 8 XCDs,
-// so workgroup b runs on XCD b % 8; give each XCD one contiguous band of tiles
-// so that neighbouring tiles, which share most of their Gaussians, share an L2.
+// so workgroup b runs on XCD b % 8.  Tiles are dealt to the XCDs in groups of
+// four consecutive tiles (neighbours share most of their Gaussians, so a group
+// shares an L2), groups interleaved over the XCDs so that dense and sparse
+// image regions are spread evenly.
 __device__ __forceinline__ int xcd_tile(int b, int nblk) {
-  const int per = nblk >> 3;
-  return (b & 7) * per + (b >> 3);
+  (void)nblk;
+  const int c = b >> 3;  // index of the workgroup within its XCD
+  return (((c >> 2) << 3) + (b & 7)) * 4 + (c & 3);
 }
 
+// One workgroup per tile, four independent waves: wave w owns the 8x8
+// quadrant w of the tile and walks the tile's list on its own, 64 instances
+// at a time.  Each lane gathers one record; a ballot keeps the instances whose
+// level-set box reaches the quadrant and the survivors are packed, in order,
+// into the wave's LDS buffer; then every lane (pixel) composites them.  The
+// next chunk's gathers are in flight meanwhile.  No workgroup barrier: a wave
+// stops as soon as its own 64 pixels are done.
 __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uint32_t* tvals,
                                                   const Rec* rec, ViewParams v, int ntile,
                                                   float* rgb, float* T_final, uint32_t* n_accum,
                                                   uint32_t* n_last,
                                                   unsigned long long* blend_ctr,
-                                                  unsigned long long* visit_ctr) {
-  __shared__ float4 s0[kBlock], s1[kBlock], s2[kBlock];
+                                                  unsigned long long* visit_ctr,
+                                                  unsigned long long* eval_ctr) {
+  __shared__ float4 s0[4][64], s1[4][64], s2[4][64];
+  __shared__ uint32_t spos[4][64];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   if (tile >= ntile) return;
   const int tx = tile % v.Tx, ty = tile / v.Tx;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
-  const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+  const int qx = tx * kTile + (wave & 1) * 8, qy = ty * kTile + (wave >> 1) * 8;
+  const int px = qx + (lane & 7);
+  const int py = qy + (lane >> 3);
   const bool inside = px < v.W && py < v.H;
   const float pcx = (float)px + 0.5f;
   const float pcy = (float)py + 0.5f;
+  const float bx0 = (float)qx + 0.5f, bx1 = (float)qx + 7.5f;
+  const float by0 = (float)qy + 0.5f, by1 = (float)qy + 7.5f;
   const uint2 rg = ranges[tile];
   float T = 1.0f;
   float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  uint32_t cnt = 0, last = 0;
+  uint32_t cnt = 0, last = 0, evals = 0;
   uint32_t visits = inside ? rg.y - rg.x : 0u;  // replaced by the stop position on termination
   bool done = !inside;
-  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += kBlock) {
-    if (__syncthreads_count(!done) == 0) break;
-    const uint32_t idx = b0 + threadIdx.x;
-    if (idx < rg.y) {
-      const Rec r = rec[tvals[idx]];
-      s0[threadIdx.x] = r.r0;
-      s1[threadIdx.x] = r.r1;
-      s2[threadIdx.x] = r.r2;
+  const unsigned long long lt = __lanemask_lt();
+  // gathers of chunk c + 1 are in flight while chunk c is composited (plain
+  // float4 registers: an aggregate here would be promoted to LDS)
+  float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
+  bool have = rg.x + lane < rg.y;
+  if (have) {
+    const Rec* rp = rec + tvals[rg.x + lane];
+    n0 = rp->r0;
+    n1 = rp->r1;
+    n2 = rp->r2;
+  }
+  for (uint32_t c0 = rg.x; c0 < rg.y && __any(!done); c0 += 64) {
+    const bool hit = have && !(n0.x + n2.z < bx0 || n0.x - n2.z > bx1 || n0.y + n2.w < by0 ||
+                               n0.y - n2.w > by1);
+    const unsigned long long m = __ballot(hit);
+    const int nl = __popcll(m);
+    if (hit) {
+      const int q = __popcll(m & lt);
+      s0[wave][q] = n0;
+      s1[wave][q] = n1;
+      s2[wave][q] = n2;
+      spos[wave][q] = c0 - rg.x + (uint32_t)lane + 1;
     }
-    __syncthreads();
-    const int nb = (int)min((uint32_t)kBlock, rg.y - b0);
-    if (!done) {
-      for (int j = 0; j < nb; ++j) {
-        const float4 a = s0[j];
-        const float4 b = s1[j];
+    const uint32_t nidx = c0 + 64 + lane;
+    have = nidx < rg.y;
+    if (have) {
+      const Rec* rp = rec + tvals[nidx];
+      n0 = rp->r0;
+      n1 = rp->r1;
+      n2 = rp->r2;
+    }
+    // branch-free compositing, four instances per step: evaluated
+    // independently, composited in order with selects; a lane that is done
+    // adds exactly zero (C + c * 0 = C, T unchanged)
+    for (int i = 0; i < nl; i += 4) {
+      float ar[4];
+      bool pre[4];
+      float4 cb[4];
+      uint32_t p1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = min(i + u, 63);
+        const float4 a = s0[wave][j];
+        const float4 b = s1[wave][j];
         const float dx = pcx - a.x;
         const float dy = pcy - a.y;
-        const float qx = dx * dx, qy = dy * dy, qxy = dx * dy;
-        const float e = -0.5f * (a.z * qx + b.x * qy);
+        const float qxx = dx * dx, qyy = dy * dy, qxy = dx * dy;
+        const float e = -0.5f * (a.z * qxx + b.x * qyy);
         const float power = e - a.w * qxy;
-        if (power > 0.0f || power < b.z) continue;
-        const float ar = b.y * exp_c(power);
-        if (ar < kAlphaMin) continue;
-        const float al = fminf(kAlphaMax, ar);
-        const float Tn = T * (1.0f - al);
-        if (Tn < kTMin) {
-          done = true;
-          visits = b0 - rg.x + (uint32_t)j + 1;
-          break;
-        }
-        const float w = al * T;
-        const float4 c = s2[j];
-        C0 = C0 + b.w * w;
-        C1 = C1 + c.x * w;
-        C2 = C2 + c.y * w;
-        T = Tn;
-        ++cnt;
-        last = b0 - rg.x + (uint32_t)j + 1;
+        ar[u] = b.y * exp_c(power);
+        pre[u] = (i + u < nl) && !(power > 0.0f) && !(power < b.z) && !(ar[u] < kAlphaMin);
+        cb[u] = make_float4(b.w, s2[wave][j].x, s2[wave][j].y, 0.0f);
+        p1[u] = spos[wave][j];
       }
+      bool any_stop = false;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool ok = pre[u] && !done;
+        const float al = fminf(kAlphaMax, ar[u]);
+        const float Tn = T * (1.0f - al);
+        const bool stop = ok && Tn < kTMin;
+        const bool acc = ok && !stop;
+        const float w = acc ? al * T : 0.0f;
+        C0 = C0 + cb[u].x * w;
+        C1 = C1 + cb[u].y * w;
+        C2 = C2 + cb[u].z * w;
+        T = acc ? Tn : T;
+        cnt += acc ? 1u : 0u;
+        evals += (i + u < nl && !done) ? 1u : 0u;
+        last = acc ? p1[u] : last;
+        visits = stop ? p1[u] : visits;
+        done = done || stop;
+        any_stop = any_stop || stop;
+      }
+      if (__any(any_stop) && __all(done)) break;  // both votes are wave-uniform
     }
   }
   if (inside) {
@@ -253,15 +332,17 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
     n_accum[pix] = cnt;
     n_last[pix] = last;
   }
-  // per-workgroup blend count (wave reduction, one atomic per wave)
-  unsigned long long c64 = cnt, v64 = visits;
+  // per-wave counts (one atomic per wave)
+  unsigned long long c64 = cnt, v64 = visits, e64 = evals;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     c64 += __shfl_xor(c64, o, 64);
     v64 += __shfl_xor(v64, o, 64);
+    e64 += __shfl_xor(e64, o, 64);
   }
   if (lane == 0 && c64) atomicAdd(blend_ctr, c64);
   if (lane == 0 && v64) atomicAdd(visit_ctr, v64);
+  if (lane == 0 && e64) atomicAdd(eval_ctr, e64);
 }
 
 __global__ __launch_bounds__(kBlock) void k_debug_exp(const float* x, float* y, int64_t n) {
@@ -281,8 +362,13 @@ void launch_project(const SceneView& s, const ViewParams& v, uint8_t* sel, uint3
                     uint32_t* depthkey, Rec* rec, uint2* rect, uint32_t* blk_vis,
                     unsigned long long* n_sel_ctr, hipStream_t st) {
   if (s.n == 0) return;
-  hipLaunchKernelGGL(k_project, dim3(grid_for(s.n)), dim3(kBlock), 0, st, s, v, sel, count,
-                     depthkey, rec, rect, blk_vis, n_sel_ctr);
+  const dim3 g(grid_for(s.n)), b(kBlock);
+  switch (s.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project<0>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, n_sel_ctr); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, n_sel_ctr); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, n_sel_ctr); break;
+    default: hipLaunchKernelGGL(k_project<3>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, n_sel_ctr); break;
+  }
 }
 
 void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
@@ -292,18 +378,11 @@ void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
                      blk_off, keys, vals);
 }
 
-void launch_gather_counts(const uint32_t* vals_sorted, const uint32_t* count,
-                          const uint32_t* d_nvis, int64_t nmax, uint32_t* out, hipStream_t st) {
+void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_nvis,
+                 int64_t nmax, const uint32_t* count, const uint2* rect, int Tx, uint32_t* tkeys,
+                 uint32_t* tvals, uint32_t* emit_base, hipStream_t st) {
   if (nmax == 0) return;
-  hipLaunchKernelGGL(k_gather_counts, dim3(grid_for(nmax)), dim3(kBlock), 0, st, vals_sorted,
-                     count, d_nvis, nmax, out);
-}
-
-void launch_emit(const uint32_t* vals_sorted, const uint32_t* off, const uint32_t* d_nvis,
-                 int64_t nmax, const uint2* rect, int Tx, uint32_t* tkeys, uint32_t* tvals,
-                 uint32_t* emit_base, hipStream_t st) {
-  if (nmax == 0) return;
-  hipLaunchKernelGGL(k_emit, dim3(grid_for(nmax)), dim3(kBlock), 0, st, vals_sorted, off, d_nvis,
+  hipLaunchKernelGGL(k_emit, dim3(grid_for(nmax)), dim3(kBlock), 0, st, order, off, d_nvis, count,
                      rect, Tx, tkeys, tvals, emit_base);
 }
 
@@ -319,11 +398,12 @@ void launch_ranges(const uint32_t* tkeys, uint32_t ninst, uint2* ranges, hipStre
 
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* blend_ctr, unsigned long long* visit_ctr, hipStream_t st) {
+                  unsigned long long* blend_ctr, unsigned long long* visit_ctr,
+                  unsigned long long* eval_ctr, hipStream_t st) {
   const int ntile = v.Tx * v.Ty;
-  const int nblk = (ntile + 7) / 8 * 8;
+  const int nblk = (ntile + 31) / 32 * 32;
   hipLaunchKernelGGL(k_blend, dim3(nblk), dim3(kBlock), 0, st, ranges, tvals, rec, v, ntile, rgb,
-                     T_final, n_accum, n_last, blend_ctr, visit_ctr);
+                     T_final, n_accum, n_last, blend_ctr, visit_ctr, eval_ctr);
 }
 
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st) {

@@ -145,9 +145,8 @@ int render_phase1(msgs_frame* f) {
   tmp.add(&f->dkeys[0], n * 4);
   tmp.add(&f->dkeys[1], n * 4);
   tmp.add(&f->dvals_alt, n * 4);
-  tmp.add(&f->cnt_d, n * 4);
   tmp.add(&f->scan_tmp, std::max(scan_tmp_bytes(n), scan_tmp_bytes(nb)));
-  tmp.add(&f->sort_tmp, radix_tmp_bytes(n));
+  tmp.add(&f->sort_tmp, radix_tmp_bytes(n, radix_passes(0, 32)));
   int rc = keep.alloc(f->ctx, st);
   if (rc != MSGS_OK) return rc;
   f->blocks.push_back(keep.base);
@@ -161,14 +160,13 @@ int render_phase1(msgs_frame* f) {
   mark(f, 0);
   launch_project(f->scene->view, v, f->sel, f->count, f->depthkey, f->rec, f->rect, f->blk_vis,
                  &f->ctr[0], st);
-  scan_excl_u32(f->blk_vis, f->blk_off, nullptr, nb, &f->ctr[2], f->scan_tmp, st);
+  scan_excl_u32(f->blk_vis, nullptr, f->blk_off, nullptr, nb, &f->ctr[2], f->scan_tmp, st);
   launch_compact(f->count, f->depthkey, n, f->blk_off, f->dkeys[0], dv0, st);
   mark(f, 1);
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
   radix_sort_pairs(f->dkeys[0], vin, f->dkeys[1], valt, d_nvis, n, 0, 32, f->sort_tmp, st);
   mark(f, 2);
-  launch_gather_counts(f->order, f->count, d_nvis, n, f->cnt_d, st);
-  scan_excl_u32(f->cnt_d, f->off_d, d_nvis, n, &f->ctr[3], f->scan_tmp, st);
+  scan_excl_u32(f->count, f->order, f->off_d, d_nvis, n, &f->ctr[3], f->scan_tmp, st);
   mark(f, 3);
   return MSGS_OK;
 }
@@ -191,7 +189,7 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   keep.add(&va, I * 4);
   tmp.add(&kb, I * 4);
   tmp.add(&vb, I * 4);
-  tmp.add(&stmp, radix_tmp_bytes(I));
+  tmp.add(&stmp, radix_tmp_bytes(I, radix_passes(0, bits)));
   int rc = keep.alloc(f->ctx, st);
   if (rc != MSGS_OK) return rc;
   f->blocks.push_back(keep.base);
@@ -203,7 +201,7 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   uint32_t* v1 = even ? vb : va;
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
   mark(f, 4);
-  launch_emit(f->order, f->off_d, d_nvis, n, f->rect, v.Tx, k0, v0, f->emit_base, st);
+  launch_emit(f->order, f->off_d, d_nvis, n, f->count, f->rect, v.Tx, k0, v0, f->emit_base, st);
   mark(f, 5);
   radix_sort_pairs(k0, v0, k1, v1, nullptr, I, 0, bits, stmp, st);
   mark(f, 6);
@@ -213,12 +211,12 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   launch_ranges(f->tkeys, (uint32_t)I, f->ranges, st);
   mark(f, 7);
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
-               &f->ctr[1], &f->ctr[4], st);
+               &f->ctr[1], &f->ctr[4], &f->ctr[5], st);
   mark(f, 8);
   f->ctx->cache.free(f->ctx, tmp.base, st);
   f->ctx->cache.free(f->ctx, f->tmp_block, st);
   f->tmp_block = nullptr;
-  f->blk_vis = f->blk_off = f->cnt_d = f->dvals_alt = nullptr;
+  f->blk_vis = f->blk_off = f->dvals_alt = nullptr;
   f->dkeys[0] = f->dkeys[1] = nullptr;
   f->scan_tmp = f->sort_tmp = nullptr;
   return MSGS_OK;
@@ -518,7 +516,7 @@ int msgs_frame_stats(const msgs_frame* f, msgs_stats* out) {
   if (!f || !out) return fail(MSGS_E_INVALID, "null argument");
   int rc = frame_sync(f);
   if (rc != MSGS_OK) return rc;
-  unsigned long long h[5];
+  unsigned long long h[6];
   hipError_t e = hipMemcpy(h, f->ctr, sizeof h, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "stats readback");
   for (int i = 0; i < 10; ++i) out->stage_us[i] = 0.0f;
@@ -546,6 +544,7 @@ int msgs_frame_stats(const msgs_frame* f, msgs_stats* out) {
     }
   }
   out->n_visits = (int64_t)h[4];
+  out->n_evals = (int64_t)h[5];
   out->n_gaussians = f->n;
   out->n_selected = (int64_t)h[0];
   out->n_visible = (int64_t)h[2];

@@ -47,7 +47,8 @@ struct ViewParams {
 // Projected record of a drawable Gaussian, three float4 per Gaussian index:
 //   r0 = (u_x, u_y, A11, A12)
 //   r1 = (A22, sigma, -(lnq + 2^-8), red)
-//   r2 = (green, blue, depth, 0)
+//   r2 = (green, blue, e_x, e_y) with e the conservative half extent of the
+//        level set (the same bound that chose the tile rectangle)
 struct Rec {
   float4 r0, r1, r2;
 };
@@ -272,6 +273,50 @@ __device__ __forceinline__ float coverage(float V11, float V12, float V22, bool 
     return sqrtf(t8);
   }
   return 0.0f;
+}
+
+// Bit w of the result is set when the conservative level-set box [u +- e] of
+// an instance reaches a pixel centre of quadrant w (8x8 pixels at (qx, qy) +
+// (w & 1, w >> 1) * 8) of the 16x16 tile whose first pixel is (x0, y0).
+__device__ __forceinline__ uint32_t quad_mask(float ux, float uy, float ex, float ey, int x0,
+                                              int y0) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const float bx0 = (float)(x0 + (w & 1) * 8) + 0.5f, bx1 = bx0 + 7.0f;
+    const float by0 = (float)(y0 + (w >> 1) * 8) + 0.5f, by1 = by0 + 7.0f;
+    const bool miss = ux + ex < bx0 || ux - ex > bx1 || uy + ey < by0 || uy - ey > by1;
+    m |= miss ? 0u : (1u << w);
+  }
+  return m;
+}
+
+// Order-preserving per-wave lists of a staged batch: instance t (held by
+// thread t, t < count) goes into list w when bit w of its mask is set.
+// lists[w][i] is the batch index of the i-th instance of list w, len[w] its
+// length.  Must be called by the whole workgroup (contains barriers).
+__device__ __forceinline__ void build_wave_lists(uint32_t mask, bool valid, uint8_t (*lists)[256],
+                                                 uint32_t* len, uint32_t (*wcnt)[4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long lt = __lanemask_lt();
+  uint32_t rank[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const bool p = valid && ((mask >> w) & 1u);
+    const unsigned long long b = __ballot(p);
+    rank[w] = (uint32_t)__popcll(b & lt);
+    if (lane == 0) wcnt[wave][w] = (uint32_t)__popcll(b);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    uint32_t off = 0;
+    for (int v = 0; v < wave; ++v) off += wcnt[v][w];
+    if (valid && ((mask >> w) & 1u)) lists[w][off + rank[w]] = (uint8_t)threadIdx.x;
+  }
+  if (threadIdx.x < 4) len[threadIdx.x] = wcnt[0][threadIdx.x] + wcnt[1][threadIdx.x] +
+                                          wcnt[2][threadIdx.x] + wcnt[3][threadIdx.x];
+  __syncthreads();
 }
 
 __device__ __forceinline__ int clamp_tile(float v, int T) {

@@ -70,7 +70,7 @@ struct msgs_frame {
   hipEvent_t ev[12] = {};
   bool bwd_recorded = false;
   // kept for the backward pass and the getters
-  unsigned long long* ctr = nullptr;   // [0] selected [1] blends [2] visible [3] instances [4] visits
+  unsigned long long* ctr = nullptr;   // [0] selected [1] blends [2] visible [3] instances [4] visits [5] evaluations
   uint8_t* sel = nullptr;
   uint32_t* count = nullptr;
   uint32_t* depthkey = nullptr;
@@ -91,7 +91,6 @@ struct msgs_frame {
   uint32_t* blk_off = nullptr;
   uint32_t* dkeys[2] = {nullptr, nullptr};
   uint32_t* dvals_alt = nullptr;
-  uint32_t* cnt_d = nullptr;
   void* scan_tmp = nullptr;
   void* sort_tmp = nullptr;
 };

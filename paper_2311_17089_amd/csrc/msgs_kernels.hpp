@@ -15,26 +15,26 @@ void launch_project(const SceneView& s, const ViewParams& v, uint8_t* sel, uint3
                     unsigned long long* n_sel_ctr, hipStream_t st);
 void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
                     const uint32_t* blk_off, uint32_t* keys, uint32_t* vals, hipStream_t st);
-void launch_gather_counts(const uint32_t* vals_sorted, const uint32_t* count,
-                          const uint32_t* d_nvis, int64_t nmax, uint32_t* out, hipStream_t st);
-void launch_emit(const uint32_t* vals_sorted, const uint32_t* off, const uint32_t* d_nvis,
-                 int64_t nmax, const uint2* rect, int Tx, uint32_t* tkeys, uint32_t* tvals,
-                 uint32_t* emit_base, hipStream_t st);
+void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_nvis,
+                 int64_t nmax, const uint32_t* count, const uint2* rect, int Tx, uint32_t* tkeys,
+                 uint32_t* tvals, uint32_t* emit_base, hipStream_t st);
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 void launch_ranges(const uint32_t* tkeys, uint32_t ninst, uint2* ranges, hipStream_t st);
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* blend_ctr, unsigned long long* visit_ctr, hipStream_t st);
+                  unsigned long long* blend_ctr, unsigned long long* visit_ctr,
+                  unsigned long long* eval_ctr, hipStream_t st);
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st);
 void launch_debug_log(const float* x, float* y, int64_t n, hipStream_t st);
 
 // sort.hip
 size_t scan_tmp_bytes(int64_t nmax);
-// Exclusive scan of in[0..n) into out[0..nmax) (zeros past n); n = *d_n when
-// d_n is non-null, else nmax.  *total (device u64) receives the sum.
-void scan_excl_u32(const uint32_t* in, uint32_t* out, const uint32_t* d_n, int64_t nmax,
-                   unsigned long long* total, void* tmp, hipStream_t st);
-size_t radix_tmp_bytes(int64_t nmax);
+// Exclusive scan of x[0..n) into out[0..nmax) (zeros past n), x[i] = in[i] or
+// in[gather[i]]; n = *d_n when d_n is non-null, else nmax.  *total (device
+// u64) receives the sum.  One kernel (decoupled look-back).
+void scan_excl_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const uint32_t* d_n,
+                   int64_t nmax, unsigned long long* total, void* tmp, hipStream_t st);
+size_t radix_tmp_bytes(int64_t nmax, int npass);
 // Stable LSD sort of pairs by key bits [begin_bit, end_bit).  Returns 1 when
 // the result ended in keys_alt / vals_alt, 0 when in keys / vals.
 int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,

@@ -1,31 +1,54 @@
-// Device-wide exclusive scan and stable LSD radix sort of (u32 key, u32 value)
+// Device-wide scans and the stable LSD radix sort of (u32 key, u32 value)
 // pairs for gfx950.
 //
-// Scan: reduce-then-scan over 4096-element tiles (256 threads x 16 items,
-// LDS-staged with one pad word per 16 to avoid bank conflicts); tile sums are
-// scanned by a single workgroup in u64 so that overflow of the u32 outputs is
-// detectable from the u64 total.
+// Ordering across workgroups uses decoupled look-back: a workgroup takes a
+// ticket from a device counter when it starts and processes the tile with
+// that number, publishes its tile aggregate, then walks back over the status
+// words of lower tickets until it meets an inclusive prefix.  A workgroup only
+// ever waits on tickets taken before its own, i.e. on workgroups that are
+// already running and publish their aggregate without waiting for anything,
+// so every wait ends.  Status words are 64-bit: flag in bits 62-63 (0 = not
+// ready, 1 = aggregate, 2 = inclusive prefix), value in the low bits; they are
+// zeroed before each use.
 //
-// Radix sort: per pass, (1) per-tile digit histograms into a digit-major
-// table, (2) exclusive scan of that table, (3) a stable scatter.  In (3) each
-// wave64 owns 1024 consecutive items and ranks its 64-item rounds with a
-// multi-split from wave ballots (one ballot per digit bit, no block barrier per
-// round); per-wave running digit counts live in LDS, and a single cross-wave
-// prefix per digit orders the four waves.  The element count may live on the
-// device (grids are sized by an upper bound; items past the count are ignored).
+// Radix sort (onesweep): one read of the keys builds the digit histograms of
+// all passes; each pass is then a single kernel: load a tile, rank it with a
+// wave multi-split (one ballot per digit bit, per-wave running digit counts in
+// LDS), publish per-digit tile counts, look back per digit, reorder the tile by
+// digit in LDS and write it out in contiguous runs per digit.
 #include "msgs_device.hpp"
 #include "msgs_kernels.hpp"
 
 namespace msgs {
 
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems;  // 4096
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kBlock * kSortItems;  // 4096
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+constexpr unsigned long long kFlagA = 1ull << 62;
+constexpr unsigned long long kFlagP = 2ull << 62;
+constexpr unsigned long long kValMask = (1ull << 62) - 1;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;  // 4096
 
-__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+__device__ __forceinline__ unsigned long long ld_status(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_status(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of the values published by the tickets before `t` for one
+// column of the status table (row stride `stride`).
+__device__ __forceinline__ unsigned long long look_back(const unsigned long long* status,
+                                                        int64_t stride, int64_t t) {
+  unsigned long long excl = 0;
+  for (int64_t p = t - 1; p >= 0; --p) {
+    unsigned long long s;
+    while (((s = ld_status(status + p * stride)) >> 62) == 0) __builtin_amdgcn_s_sleep(1);
+    excl += s & kValMask;
+    if ((s >> 62) == 2) break;
+  }
+  return excl;
+}
 
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
@@ -37,7 +60,7 @@ __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
   return v;
 }
 
-// Block-wide exclusive scan of one value per thread; returns the block total.
+// Block-wide exclusive scan of one value per thread; `total` gets the sum.
 template <typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T* wtot, T& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -55,65 +78,33 @@ __device__ __forceinline__ T block_excl_scan(T v, T* wtot, T& total) {
   return base + inc - v;
 }
 
-template <typename TI>
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const TI* in, const uint32_t* d_n,
-                                                        int64_t nmax,
-                                                        unsigned long long* partial) {
-  __shared__ unsigned long long wtot[kBlock / 64];
-  const int64_t n = d_n ? (int64_t)*d_n : nmax;
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  unsigned long long s = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    const int64_t idx = base + i * kBlock + threadIdx.x;
-    if (idx < n) s += (unsigned long long)in[idx];
-  }
-  unsigned long long tot;
-  block_excl_scan(s, wtot, tot);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
+__device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
 
-// In-place exclusive scan of `m` u64 values by one workgroup; writes the total.
-__global__ __launch_bounds__(kBlock) void k_scan_single_u64(unsigned long long* data, int64_t m,
-                                                            unsigned long long* total_out) {
-  __shared__ unsigned long long wtot[kBlock / 64];
-  unsigned long long carry = 0;
-  for (int64_t c0 = 0; c0 < m; c0 += kBlock * 4) {
-    unsigned long long v[4];
-    unsigned long long s = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t idx = c0 + threadIdx.x * 4 + i;
-      v[i] = idx < m ? data[idx] : 0ull;
-      s += v[i];
-    }
-    unsigned long long tot;
-    unsigned long long ex = block_excl_scan(s, wtot, tot);
-    unsigned long long run = carry + ex;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t idx = c0 + threadIdx.x * 4 + i;
-      if (idx < m) data[idx] = run;
-      run += v[i];
-    }
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
-template <typename TI>
-__global__ __launch_bounds__(kBlock) void k_scan_apply(const TI* in, uint32_t* out,
-                                                       const uint32_t* d_n, int64_t nmax,
-                                                       const unsigned long long* partial) {
+// ------------------------------------------------------------------ scan
+// Exclusive scan, one kernel: out[j] = sum_{i<j} x_i with x_i = in[i], or
+// x_i = in[gather[i]] when gather is non-null; n = *d_n or nmax; outputs past
+// n (up to nmax) are zero; *total = sum.
+__global__ __launch_bounds__(kBlock) void k_scan_lb(const uint32_t* in, const uint32_t* gather,
+                                                    const uint32_t* d_n, int64_t nmax,
+                                                    uint32_t* out, unsigned long long* total,
+                                                    unsigned long long* status,
+                                                    uint32_t* ticket) {
   __shared__ uint32_t buf[kScanTile + kScanTile / 16];
   __shared__ uint32_t wtot[kBlock / 64];
+  __shared__ int64_t s_tile;
+  __shared__ unsigned long long s_base;
+  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+  __syncthreads();
+  const int64_t t = s_tile;
   const int64_t n = d_n ? (int64_t)*d_n : nmax;
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const int64_t base = t * kScanTile;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int e = i * kBlock + threadIdx.x;
     const int64_t idx = base + e;
-    buf[pad16(e)] = idx < n ? (uint32_t)in[idx] : 0u;
+    uint32_t x = 0;
+    if (idx < n) x = gather ? in[gather[idx]] : in[idx];
+    buf[pad16(e)] = x;
   }
   __syncthreads();
   uint32_t loc[kScanItems];
@@ -124,7 +115,21 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const TI* in, uint32_t* o
     s += loc[i];
   }
   uint32_t tot;
-  uint32_t run = block_excl_scan(s, wtot, tot) + (uint32_t)partial[blockIdx.x];
+  uint32_t run = block_excl_scan(s, wtot, tot);
+  if (threadIdx.x == 0) {
+    if (t == 0) {
+      st_status(status, kFlagP | tot);
+      s_base = 0;
+    } else {
+      st_status(status + t, kFlagA | tot);
+      const unsigned long long ex = look_back(status, 1, t);
+      st_status(status + t, kFlagP | (ex + tot));
+      s_base = ex;
+    }
+    if (t == (int64_t)gridDim.x - 1 && total) *total = s_base + tot;
+  }
+  __syncthreads();
+  run += (uint32_t)s_base;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     buf[pad16(threadIdx.x * kScanItems + i)] = run;
@@ -139,70 +144,91 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const TI* in, uint32_t* o
   }
 }
 
-size_t scan_tmp_bytes(int64_t nmax) {
-  const int64_t nb = (nmax + kScanTile - 1) / kScanTile;
-  return (size_t)(nb + 1) * sizeof(unsigned long long);
-}
-
-void scan_excl_u32(const uint32_t* in, uint32_t* out, const uint32_t* d_n, int64_t nmax,
-                   unsigned long long* total, void* tmp, hipStream_t st) {
-  const int64_t nb = (nmax + kScanTile - 1) / kScanTile;
-  unsigned long long* partial = (unsigned long long*)tmp;
-  if (nb == 0) {
-    hipLaunchKernelGGL(k_scan_single_u64, dim3(1), dim3(kBlock), 0, st, partial, (int64_t)0, total);
-    return;
-  }
-  hipLaunchKernelGGL(k_scan_reduce<uint32_t>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, d_n,
-                     nmax, partial);
-  hipLaunchKernelGGL(k_scan_single_u64, dim3(1), dim3(kBlock), 0, st, partial, nb, total);
-  hipLaunchKernelGGL(k_scan_apply<uint32_t>, dim3((unsigned)nb), dim3(kBlock), 0, st, in, out, d_n,
-                     nmax, partial);
-}
-
 // ------------------------------------------------------------------ radix sort
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* keys, const uint32_t* d_n,
-                                                       int64_t nmax, int shift, int nbits,
-                                                       uint32_t* hist, int nblk) {
-  __shared__ uint32_t h[kBlock / 64][kRadix];
+// Digit histograms of every pass, one read of the keys: workgroup b counts a
+// contiguous chunk into its own row of rows[pass][b][digit] (no global atomics).
+constexpr int kHistBlocks = 256;
+__global__ __launch_bounds__(kBlock) void k_os_hist(const uint32_t* keys, const uint32_t* d_n,
+                                                    int64_t nmax, int begin_bit, int end_bit,
+                                                    uint32_t* rows) {
+  __shared__ uint32_t h[4][kBlock / 64][kRadix];
   const int wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) h[w][threadIdx.x] = 0;
+  const int npass = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
+  for (int p = 0; p < 4; ++p)
+    for (int w = 0; w < kBlock / 64; ++w) h[p][w][threadIdx.x] = 0;
   __syncthreads();
   const int64_t n = d_n ? (int64_t)*d_n : nmax;
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  const uint32_t mask = (1u << nbits) - 1u;
-#pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
-    const int64_t idx = base + i * kBlock + threadIdx.x;
-    if (idx < n) atomicAdd(&h[wave][(keys[idx] >> shift) & mask], 1u);
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk;
+  const int64_t i1 = min(n, i0 + chunk);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    const uint32_t key = keys[i];
+    for (int p = 0; p < npass; ++p) {
+      const int sh = begin_bit + p * kRadixBits;
+      const int nb = min(kRadixBits, end_bit - sh);
+      atomicAdd(&h[p][wave][(key >> sh) & ((1u << nb) - 1u)], 1u);
+    }
   }
   __syncthreads();
-  uint32_t c = 0;
+  for (int p = 0; p < npass; ++p) {
+    uint32_t c = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) c += h[w][threadIdx.x];
-  hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = c;
+    for (int w = 0; w < kBlock / 64; ++w) c += h[p][w][threadIdx.x];
+    rows[((int64_t)p * gridDim.x + blockIdx.x) * kRadix + threadIdx.x] = c;
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* keys_in,
-                                                          const uint32_t* vals_in,
-                                                          uint32_t* keys_out, uint32_t* vals_out,
-                                                          const uint32_t* d_n, int64_t nmax,
-                                                          int shift, int nbits,
-                                                          const uint32_t* hist_scanned, int nblk) {
+// Digit totals of each pass (sum over the histogram rows), exclusive-scanned
+// into the global start of every digit (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_os_hist_scan(const uint32_t* rows, int nrows,
+                                                         uint32_t* gstart, int npass) {
+  __shared__ uint32_t wtot[kBlock / 64];
+  for (int p = 0; p < npass; ++p) {
+    const uint32_t* rp = rows + (int64_t)p * nrows * kRadix + threadIdx.x;
+    uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int r = 0;
+    for (; r + 8 <= nrows; r += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += rp[(int64_t)(r + u) * kRadix];
+    }
+    for (; r < nrows; ++r) acc[0] += rp[(int64_t)r * kRadix];
+    const uint32_t v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(v, wtot, tot);
+    gstart[p * kRadix + threadIdx.x] = ex;
+  }
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
+                                                    const uint32_t* vals_in, uint32_t* keys_out,
+                                                    uint32_t* vals_out, const uint32_t* d_n,
+                                                    int64_t nmax, int shift, int nbits,
+                                                    const uint32_t* gstart,
+                                                    unsigned long long* status,
+                                                    uint32_t* ticket) {
+  constexpr int TILE = kBlock * ITEMS;
   __shared__ uint32_t cnt[kBlock / 64][kRadix];
-  __shared__ uint32_t gbase[kRadix];
+  __shared__ uint32_t ldig[kRadix];
+  __shared__ uint32_t gdig[kRadix];
+  __shared__ uint32_t wtot[kBlock / 64];
+  __shared__ uint32_t ks[TILE];
+  __shared__ uint32_t vs[TILE];
+  __shared__ int64_t s_tile;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
 #pragma unroll
   for (int w = 0; w < kBlock / 64; ++w) cnt[w][threadIdx.x] = 0;
-  gbase[threadIdx.x] = hist_scanned[(int64_t)threadIdx.x * nblk + blockIdx.x];
   __syncthreads();
+  const int64_t t = s_tile;
   const int64_t n = d_n ? (int64_t)*d_n : nmax;
-  const int64_t wbase = (int64_t)blockIdx.x * kSortTile + (int64_t)wave * (64 * kSortItems);
+  const int64_t tbase = t * TILE;
+  const int64_t wbase = tbase + (int64_t)wave * (64 * ITEMS);
   const uint32_t mask = (1u << nbits) - 1u;
   const unsigned long long lt = __lanemask_lt();
-  uint32_t k_[kSortItems], v_[kSortItems], r_[kSortItems];
+  uint32_t k_[ITEMS], v_[ITEMS], r_[ITEMS];
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const int64_t idx = wbase + i * 64 + lane;
     const bool valid = idx < n;
     const uint32_t key = valid ? keys_in[idx] : 0u;
@@ -218,66 +244,120 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* keys_i
     uint32_t before = 0;
     if (valid) before = cnt[wave][d];
     r_[i] = before + (uint32_t)__popcll(m & lt);
-    const bool leader = valid && (lane == __ffsll((long long)m) - 1);
-    if (leader) cnt[wave][d] = before + (uint32_t)__popcll(m);
+    if (valid && lane == __ffsll((long long)m) - 1) cnt[wave][d] = before + (uint32_t)__popcll(m);
   }
   __syncthreads();
-  {
-    uint32_t run = 0;
+  // per digit: cross-wave prefix, tile count, local digit start
+  const int d = threadIdx.x;
+  uint32_t bt = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-      const uint32_t c = cnt[w][threadIdx.x];
-      cnt[w][threadIdx.x] = run;
-      run += c;
-    }
+  for (int w = 0; w < kBlock / 64; ++w) {
+    const uint32_t c = cnt[w][d];
+    cnt[w][d] = bt;
+    bt += c;
   }
+  uint32_t tot;
+  ldig[d] = block_excl_scan(bt, wtot, tot);
+  unsigned long long* st = status + t * kRadix + d;
+  unsigned long long excl = 0;
+  if (t == 0) {
+    st_status(st, kFlagP | bt);
+  } else {
+    st_status(st, kFlagA | bt);
+    excl = look_back(status + d, kRadix, t);
+    st_status(st, kFlagP | (excl + bt));
+  }
+  gdig[d] = gstart[d] + (uint32_t)excl;
   __syncthreads();
+  // reorder the tile by digit in LDS
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const int64_t idx = wbase + i * 64 + lane;
     if (idx < n) {
-      const uint32_t d = (k_[i] >> shift) & mask;
-      const uint32_t pos = gbase[d] + cnt[wave][d] + r_[i];
-      keys_out[pos] = k_[i];
-      vals_out[pos] = v_[i];
+      const uint32_t dd = (k_[i] >> shift) & mask;
+      const uint32_t lp = ldig[dd] + cnt[wave][dd] + r_[i];
+      ks[lp] = k_[i];
+      vs[lp] = v_[i];
     }
+  }
+  __syncthreads();
+  const int64_t rem = n - tbase;
+  const int cntile = rem <= 0 ? 0 : (rem >= TILE ? TILE : (int)rem);
+  for (int p = threadIdx.x; p < cntile; p += kBlock) {
+    const uint32_t key = ks[p];
+    const uint32_t dd = (key >> shift) & mask;
+    const uint32_t g = gdig[dd] + ((uint32_t)p - ldig[dd]);
+    keys_out[g] = key;
+    vals_out[g] = vs[p];
   }
 }
 
-size_t radix_tmp_bytes(int64_t nmax) {
-  const int64_t nblk = (nmax + kSortTile - 1) / kSortTile;
-  const int64_t m = (int64_t)kRadix * (nblk > 0 ? nblk : 1);
-  return (size_t)m * sizeof(uint32_t) * 2 + scan_tmp_bytes(m) + 64;
+static inline int sort_items(int64_t nmax) { return nmax >= (4ll << 20) ? 16 : 8; }
+
+size_t scan_tmp_bytes(int64_t nmax) {
+  const int64_t nb = (nmax + kScanTile - 1) / kScanTile;
+  return (size_t)(nb > 0 ? nb : 1) * 8 + 256;
+}
+
+void scan_excl_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const uint32_t* d_n,
+                   int64_t nmax, unsigned long long* total, void* tmp, hipStream_t st) {
+  const int64_t nb = (nmax + kScanTile - 1) / kScanTile;
+  unsigned long long* status = (unsigned long long*)tmp;
+  uint32_t* ticket = (uint32_t*)(status + (nb > 0 ? nb : 1));
+  if (nb == 0) {
+    launch_fill_u32((uint32_t*)total, 2, 0u, st);
+    return;
+  }
+  launch_fill_u32((uint32_t*)status, 2 * nb + 2, 0u, st);
+  hipLaunchKernelGGL(k_scan_lb, dim3((unsigned)nb), dim3(kBlock), 0, st, in, gather, d_n, nmax,
+                     out, total, status, ticket);
+}
+
+size_t radix_tmp_bytes(int64_t nmax, int npass) {
+  const int items = sort_items(nmax);
+  const int64_t nblk = (nmax + kBlock * items - 1) / (kBlock * items);
+  return (size_t)npass * kRadix * 4 + (size_t)npass * (nblk > 0 ? nblk : 1) * kRadix * 8 + 64 * 4 +
+         (size_t)npass * kHistBlocks * kRadix * 4;
 }
 
 int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                      const uint32_t* d_n, int64_t nmax, int begin_bit, int end_bit, void* tmp,
                      hipStream_t st) {
   if (nmax == 0 || end_bit <= begin_bit) return 0;
-  const int nblk = (int)((nmax + kSortTile - 1) / kSortTile);
-  const int64_t m = (int64_t)kRadix * nblk;
-  uint32_t* hist = (uint32_t*)tmp;
-  uint32_t* hist_s = hist + m;
-  void* stmp = (void*)(hist_s + m);
-  unsigned long long* total = (unsigned long long*)((char*)stmp + scan_tmp_bytes(m));
+  const int npass = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
+  const int items = sort_items(nmax);
+  const int tile = kBlock * items;
+  const int64_t nblk = (nmax + tile - 1) / tile;
+  uint32_t* ghist = (uint32_t*)tmp;
+  unsigned long long* status = (unsigned long long*)(ghist + npass * kRadix);
+  uint32_t* tickets = (uint32_t*)(status + npass * nblk * kRadix);
+  uint32_t* rows = tickets + 64;
+  const int64_t zero_words = npass * kRadix + 2 * npass * nblk * kRadix + 64;
+  launch_fill_u32((uint32_t*)tmp, zero_words, 0u, st);
+  const int hgrid = (int)std::min<int64_t>((nmax + 4095) / 4096, kHistBlocks);
+  hipLaunchKernelGGL(k_os_hist, dim3(hgrid), dim3(kBlock), 0, st, keys, d_n, nmax, begin_bit,
+                     end_bit, rows);
+  hipLaunchKernelGGL(k_os_hist_scan, dim3(1), dim3(kBlock), 0, st, rows, hgrid, ghist, npass);
   uint32_t* kin = keys;
   uint32_t* vin = vals;
   uint32_t* kout = keys_alt;
   uint32_t* vout = vals_alt;
-  int passes = 0;
-  for (int b = begin_bit; b < end_bit; b += kRadixBits) {
-    const int nbits = end_bit - b < kRadixBits ? end_bit - b : kRadixBits;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kBlock), 0, st, kin, d_n, nmax, b, nbits,
-                       hist, nblk);
-    scan_excl_u32(hist, hist_s, nullptr, m, total, stmp, st);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kBlock), 0, st, kin, vin, kout, vout, d_n,
-                       nmax, b, nbits, hist_s, nblk);
-    uint32_t* t;
-    t = kin; kin = kout; kout = t;
-    t = vin; vin = vout; vout = t;
-    ++passes;
+  for (int p = 0; p < npass; ++p) {
+    const int b = begin_bit + p * kRadixBits;
+    const int nbits = std::min(kRadixBits, end_bit - b);
+    if (items == 16)
+      hipLaunchKernelGGL(k_os_pass<16>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, vin, kout,
+                         vout, d_n, nmax, b, nbits, ghist + p * kRadix,
+                         status + (int64_t)p * nblk * kRadix, tickets + p);
+    else
+      hipLaunchKernelGGL(k_os_pass<8>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, vin, kout,
+                         vout, d_n, nmax, b, nbits, ghist + p * kRadix,
+                         status + (int64_t)p * nblk * kRadix, tickets + p);
+    uint32_t* tt;
+    tt = kin; kin = kout; kout = tt;
+    tt = vin; vin = vout; vout = tt;
   }
-  return passes & 1;  // 1: the result is in the *_alt buffers
+  return npass & 1;
 }
 
 }  // namespace msgs

@@ -47,6 +47,7 @@ class RenderOpts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n_gaussians", C.c_int64), ("n_selected", C.c_int64), ("n_visible", C.c_int64),
                 ("n_instances", C.c_int64), ("n_blends", C.c_int64), ("n_visits", C.c_int64),
+                ("n_evals", C.c_int64),
                 ("width", C.c_int), ("height", C.c_int), ("tiles_x", C.c_int), ("tiles_y", C.c_int),
                 ("stage_us", C.c_float * 10)]
 
