@@ -103,6 +103,49 @@ def cpu_baseline(seconds_hint=True):
                       f"{blends} blends in {dt:.1f} s (includes the oracle's per-call projection)"}
 
 
+def serving_replay(M, G, n_req=512, rate_hz=200.0, inflight=4, selective=True, log=None):
+    """Poisson stream of render requests against the resident 3M-Gaussian,
+    4-level scene: poses uniform on a sphere of radius 2-12 looking at the
+    origin, 1920x1080 downscaled by a factor uniform over {1, 2, ..., 128}.
+    Requests are submitted at their arrival times to the continuous-batching
+    server; latency = completion - submission."""
+    import numpy as np
+    import torch
+    if not hasattr(serving_replay, "scene"):
+        ctx = M.Context(0)
+        sc = G.large_scene(3_000_000, 4, 3)
+        dsc = M.DeviceScene(ctx, sc)
+        M.calibrate(ctx, dsc, G.calibration_cameras(1003, 1920, 1080, 2250.0))
+        serving_replay.scene = (ctx, dsc)
+    ctx, dsc = serving_replay.scene
+    stream = G.request_stream(seed=4, n=n_req, rate_hz=rate_hz)
+    outs = [torch.empty((cam.height // d, cam.width // d, 3), device="cuda") for _, cam, d in stream]
+    torch.cuda.synchronize()
+    srv = M.Server(ctx, dsc, max_inflight=inflight)
+    done = []
+    t0 = time.perf_counter()
+    for i, (arr, cam, d) in enumerate(stream):
+        while time.perf_counter() - t0 < arr:
+            done += srv.poll(64, 0)
+            time.sleep(0.0002)
+        srv.submit(cam, outs[i], i, downscale=d, selective=selective)
+    while len(done) < n_req:
+        done += srv.poll(64, 1_000_000)
+    srv.close()
+    lat = np.array([(d["t_done_us"] - d["t_submit_us"]) / 1e3 for d in done])
+    ok = all(d["status"] == 0 for d in done)
+    first = min(d["t_submit_us"] for d in done)
+    last = max(d["t_done_us"] for d in done)
+    per_ds = {}
+    for d in done:
+        per_ds.setdefault(stream[d["req_id"]][2], []).append((d["t_done_us"] - d["t_submit_us"]) / 1e3)
+    return {"requests": n_req, "rate_hz": rate_hz, "inflight": inflight, "all_ok": ok,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "frames_per_s": n_req / ((last - first) / 1e6),
+            "blends": int(sum(d["n_blends"] for d in done)),
+            "p50_ms_by_downscale": {str(k): float(np.percentile(v, 50)) for k, v in sorted(per_ds.items())}}
+
+
 def traffic_for(kernel, launch):
     """HBM traffic of the dominant kernel from the committed rocprofv3 counter
     summary, if it was taken from the current kernel source."""
@@ -129,6 +172,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
     ap.add_argument("--serial", action="store_true",
                     help="render the frames of a step one after another on one stream")
@@ -286,6 +330,11 @@ def main():
         "stage_us_per_step": {s: round(v, 2) for s, v in stage_tot.items()},
         "per_downscale": per_ds,
     }
+    if not args.no_serving:
+        print("bench: serving replay (3M-Gaussian scene, 512 requests at 200/s)", file=sys.stderr,
+              flush=True)
+        out["serving"] = {"selective": serving_replay(M, G, selective=True),
+                          "single_scale": serving_replay(M, G, selective=False)}
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

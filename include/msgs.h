@@ -209,6 +209,43 @@ int msgs_frame_get_keys(const msgs_frame* f, uint64_t* keys, uint32_t* vals, siz
 int msgs_frame_get_state(const msgs_frame* f, float* T_final, uint32_t* n_contrib);
 int msgs_frame_get_ranges(const msgs_frame* f, uint32_t* ranges, size_t cap, size_t* n);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous-batching server over one resident scene.  max_inflight slots,
+ * each a host worker thread with its own HIP stream, take queued requests in
+ * FIFO order as soon as they are free, so requests that arrive while others
+ * are on the GPU run concurrently with them.  Admission is by device memory:
+ * a request's frame allocates from the context budget (per-Gaussian buffers,
+ * then its tile lists once their length is known) and waits for other
+ * requests to return memory when it does not fit; if all in-flight requests
+ * wait, all but the oldest release theirs and go back to the head of the
+ * queue.  A request that cannot fit alone completes with MSGS_E_NOMEM.  Range
+ * updates are not allowed through the server (results would depend on the
+ * interleaving).  The scene and the output buffers must stay valid until the
+ * request completes.  Times are host steady-clock microseconds since the
+ * server was created. */
+typedef struct {
+  uint64_t req_id;
+  int status;          /* MSGS_OK or the request's error code */
+  double t_submit_us;  /* msgs_server_submit returned */
+  double t_admit_us;   /* per-Gaussian buffers allocated, first kernels enqueued */
+  double t_start_us;   /* a slot took the request */
+  double t_done_us;    /* output complete on the device, observed by the slot */
+  int64_t n_blends;
+} msgs_completion;
+
+int msgs_server_create(msgs_context* ctx, msgs_scene* scene, int max_inflight,
+                       msgs_server** out);
+/* Queue one render into rgb_out (device [H_d][W_d][3]); MSGS_E_BUSY when the
+ * queue (65536 requests) is full, MSGS_E_INVALID for a bad camera/options. */
+int msgs_server_submit(msgs_server* s, const msgs_camera* cam, const msgs_render_opts* opts,
+                       float* rgb_out, uint64_t req_id);
+/* Up to `max` completions; waits up to timeout_us for the first one. */
+int msgs_server_poll(msgs_server* s, msgs_completion* out, int max, int* n, int timeout_us);
+/* Requests waiting in the queue and requests being rendered. */
+int msgs_server_pending(msgs_server* s, int* queued, int* inflight);
+/* Finishes the in-flight requests, drops the queued ones, joins the slots. */
+int msgs_server_destroy(msgs_server* s);
+
 /* Device evaluation of the library's fp32 exp (domain [-5.6, 0]) and log
  * (domain (1, 256)) used by selection and blending, on device arrays of n
  * floats.  For verification of the numerics contract. */

@@ -157,9 +157,17 @@ size_t Carve::add(void** slot, size_t bytes) {
   return off;
 }
 
+thread_local AdmitWaiter* t_waiter = nullptr;
+
 int Carve::alloc(msgs_context* c, hipStream_t st) {
-  int rc = c->cache.alloc(c, &base, total, st);
-  if (rc != MSGS_OK) return rc;
+  for (;;) {
+    int rc = c->cache.alloc(c, &base, total, st);
+    if (rc == MSGS_OK) break;
+    if (rc != MSGS_E_NOMEM || !t_waiter) return rc;
+    const MemWait w = t_waiter->wait_for_memory();
+    if (w == MemWait::kAbort) return kRequeue;
+    if (w == MemWait::kFail) return rc;
+  }
   for (auto& p : parts) *p.first = (char*)base + p.second;
   return MSGS_OK;
 }

@@ -380,6 +380,15 @@ int msgs_scene_get_ranges(const msgs_scene* s, float* smax, float* smin) {
 int msgs_render(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
                 const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
                 void* stream) {
+  return render_internal(c, s, cam, opts, rgb_out, frame_out, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace msgs {
+int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
+                    const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
+                    hipStream_t stream) {
   if (!c || !s || !rgb_out) return fail(MSGS_E_INVALID, "null argument");
   if (s->ctx != c) return fail(MSGS_E_INVALID, "scene belongs to another context");
   msgs_render_opts o;
@@ -411,6 +420,7 @@ int msgs_render(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
     }
   }
   rc = render_phase1(f);
+  if (rc == MSGS_OK && t_waiter) t_waiter->on_admitted();
   if (rc == MSGS_OK) {
     unsigned long long* hp = pinned_slot();
     if (!hp) {
@@ -442,6 +452,9 @@ int msgs_render(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
   *frame_out = f;
   return MSGS_OK;
 }
+}  // namespace msgs
+
+extern "C" {
 
 int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_drgb,
                          const msgs_grads* out, void* stream) {

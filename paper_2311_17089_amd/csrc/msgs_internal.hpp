@@ -96,6 +96,20 @@ struct msgs_frame {
 };
 
 namespace msgs {
+// Admission hook of the server: when a frame allocation exceeds the context
+// budget, the allocation asks the request's waiter what to do.
+enum class MemWait { kRetry, kAbort, kFail };
+struct AdmitWaiter {
+  virtual MemWait wait_for_memory() = 0;
+  virtual void on_admitted() = 0;
+  virtual ~AdmitWaiter() = default;
+};
+extern thread_local AdmitWaiter* t_waiter;
+constexpr int kRequeue = -100;  // internal: request aborted to break an admission cycle
+
+int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
+                    const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
+                    hipStream_t stream);
 extern thread_local std::string t_err;
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);

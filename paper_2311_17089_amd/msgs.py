@@ -62,6 +62,9 @@ class Completion(C.Structure):
                 ("t_admit_us", C.c_double), ("t_start_us", C.c_double), ("t_done_us", C.c_double),
                 ("n_blends", C.c_int64)]
 
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
 
 _lib = None
 
@@ -89,6 +92,7 @@ EXPORTS = {
     "msgs_server_create": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "msgs_server_submit": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64], C.c_int),
     "msgs_server_poll": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int], C.c_int),
+    "msgs_server_pending": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "msgs_server_destroy": ([C.c_void_p], C.c_int),
 }
 
@@ -364,3 +368,44 @@ def render_differentiable(ctx: Context, means, scales, quats, opacity, sh, level
     (linear), quats [4,n] (raw), opacity [n] (sigma) and sh [(D+1)^2*3, n]."""
     return _RenderFn.apply(means, scales, quats, opacity, sh,
                            (ctx, level, s_max, s_min, n_levels, sh_degree, cam, kw))
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching render server over one resident scene (see
+    msgs_server_* in msgs.h)."""
+
+    def __init__(self, ctx: Context, scene: DeviceScene, max_inflight: int = 4):
+        self.ctx, self.scene = ctx, scene
+        h = C.c_void_p()
+        check(lib().msgs_server_create(ctx.h, scene.h, int(max_inflight), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, cam, out: torch.Tensor, req_id: int, downscale=1, selective=True,
+               lowpass=0.3, near=0.2, bg=(0.0, 0.0, 0.0)) -> None:
+        assert out.is_contiguous() and out.dtype == torch.float32
+        c = camera_c(cam)
+        o = opts_c(downscale, selective, False, lowpass, near, bg)
+        check(lib().msgs_server_submit(self.h, C.byref(c), C.byref(o), C.c_void_p(out.data_ptr()),
+                                       C.c_uint64(req_id)))
+        self._keep[req_id] = out
+
+    def poll(self, max_n: int = 64, timeout_us: int = 0):
+        arr = (Completion * max_n)()
+        n = C.c_int()
+        check(lib().msgs_server_poll(self.h, arr, max_n, C.byref(n), int(timeout_us)))
+        res = [arr[i].as_dict() for i in range(n.value)]
+        for r in res:
+            self._keep.pop(r["req_id"], None)
+        return res
+
+    def pending(self):
+        q, f = C.c_int(), C.c_int()
+        check(lib().msgs_server_pending(self.h, C.byref(q), C.byref(f)))
+        return q.value, f.value
+
+    def close(self):
+        if self.h:
+            check(lib().msgs_server_destroy(self.h))
+            self.h = None
