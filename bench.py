@@ -38,8 +38,15 @@ ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 # accumulated contribution adds exp (19), alpha, transmittance and colour (10).
 FLOPS_PER_VISIT = 11
 FLOPS_PER_BLEND = 29
-STAGES = ("project", "depth_sort", "count_scan", "emit", "tile_sort", "ranges", "blend",
-          "blend_bwd", "chain_bwd")
+# the adjoint per accumulated contribution: exp (19); alpha, 1/(1-alpha) and
+# the replayed transmittance (6); colour and alpha partials with the suffix
+# colour update (24); partials of sigma, centre and conic (16); and the sum of
+# the nine partials over the tile's pixels (9)
+FLOPS_PER_BLEND_BWD = 74
+# stage name -> index into the library's per-frame stage timings
+STAGE_IDX = {"project": 0, "depth_sort": 1, "count_scan": 2, "emit": 3, "tile_sort": 4,
+             "ranges": 5, "blend": 6, "zero_bwd": 10, "blend_bwd": 7, "chain_bwd": 8}
+STAGES = tuple(STAGE_IDX)
 
 
 def c2_camera(G):
@@ -63,8 +70,8 @@ def stage_bytes(st, n, sh_degree, passes_depth, passes_tile):
         "emit": nv * (4 + 4 + 8 + 4) + I * 8,
         "tile_sort": passes_tile * I * (4 + 16),
         "ranges": I * 4 + ntile * 8,
-        # partials written by the replay: 36 B per instance (plus the zero fill)
-        "blend_bwd_bytes": I * 36 * 2,
+        # zero fill of the per-instance partials (three float4 each)
+        "zero_bwd": I * 48,
         # read the partials and tile counts, write/read the per-Gaussian sums,
         # read the parameters again, write every gradient plane
         "chain_bwd": I * 36 + n * 8 + n * 72 + n * (53 + 12 * K) + n * (44 + 12 * K),
@@ -103,12 +110,13 @@ def cpu_baseline(seconds_hint=True):
                       f"{blends} blends in {dt:.1f} s (includes the oracle's per-call projection)"}
 
 
-def serving_replay(M, G, n_req=512, rate_hz=200.0, inflight=4, selective=True, log=None):
+def serving_replay(M, G, n_req=512, rate_hz=200.0, inflight=4, selective=True):
     """Poisson stream of render requests against the resident 3M-Gaussian,
     4-level scene: poses uniform on a sphere of radius 2-12 looking at the
     origin, 1920x1080 downscaled by a factor uniform over {1, 2, ..., 128}.
     Requests are submitted at their arrival times to the continuous-batching
-    server; latency = completion - submission."""
+    server; latency = completion - scheduled arrival (the server's completion
+    minus submission time, plus how late the submission was)."""
     import numpy as np
     import torch
     if not hasattr(serving_replay, "scene"):
@@ -123,25 +131,32 @@ def serving_replay(M, G, n_req=512, rate_hz=200.0, inflight=4, selective=True, l
     torch.cuda.synchronize()
     srv = M.Server(ctx, dsc, max_inflight=inflight)
     done = []
+    late = np.zeros(n_req)
     t0 = time.perf_counter()
     for i, (arr, cam, d) in enumerate(stream):
         while time.perf_counter() - t0 < arr:
             done += srv.poll(64, 0)
             time.sleep(0.0002)
+        late[i] = (time.perf_counter() - t0 - arr) * 1e3
         srv.submit(cam, outs[i], i, downscale=d, selective=selective)
     while len(done) < n_req:
         done += srv.poll(64, 1_000_000)
     srv.close()
-    lat = np.array([(d["t_done_us"] - d["t_submit_us"]) / 1e3 for d in done])
+
+    def latency(d):
+        return (d["t_done_us"] - d["t_submit_us"]) / 1e3 + late[d["req_id"]]
+
+    lat = np.array([latency(d) for d in done])
     ok = all(d["status"] == 0 for d in done)
     first = min(d["t_submit_us"] for d in done)
     last = max(d["t_done_us"] for d in done)
     per_ds = {}
     for d in done:
-        per_ds.setdefault(stream[d["req_id"]][2], []).append((d["t_done_us"] - d["t_submit_us"]) / 1e3)
+        per_ds.setdefault(stream[d["req_id"]][2], []).append(latency(d))
     return {"requests": n_req, "rate_hz": rate_hz, "inflight": inflight, "all_ok": ok,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "frames_per_s": n_req / ((last - first) / 1e6),
+            "max_submit_lag_ms": float(late.max()),
             "blends": int(sum(d["n_blends"] for d in done)),
             "p50_ms_by_downscale": {str(k): float(np.percentile(v, 50)) for k, v in sorted(per_ds.items())}}
 
@@ -174,6 +189,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run one serial step and a 1 GiB elementwise copy, for HBM counter runs")
     ap.add_argument("--serial", action="store_true",
                     help="render the frames of a step one after another on one stream")
     args = ap.parse_args()
@@ -204,19 +221,28 @@ def main():
     streams = {ds: torch.cuda.Stream() for ds in DOWNSCALES}
     pool = ThreadPoolExecutor(max_workers=len(DOWNSCALES))
 
+    # per-launch device time of every stage, from the library's own HIP events
+    # on the frame's stream, accumulated over the kernel-timing steps
+    stage_acc = {ds: {s: 0.0 for s in STAGES} for ds in DOWNSCALES}
+
+    def run_frame(ds, st=None, prof=False):
+        _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, profile=prof, stream=st)
+        M.render_backward(ctx, fr, dls[ds], stream=st)
+        if prof:
+            us = fr.stats()["stage_us"]  # waits for this frame's stream
+            for s in STAGES:
+                stage_acc[ds][s] += us[STAGE_IDX[s]]
+        fr.release()
+
     def frame(ds):
         st = streams[ds]
         with torch.cuda.stream(st):
-            _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, stream=st)
-            M.render_backward(ctx, fr, dls[ds], stream=st)
-            fr.release()
+            run_frame(ds, st)
 
-    def step():
-        if args.serial:
+    def step(prof=False):
+        if args.serial or prof:
             for ds in DOWNSCALES:
-                _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True)
-                M.render_backward(ctx, fr, dls[ds])
-                fr.release()
+                run_frame(ds, prof=prof)
             return
         for f in [pool.submit(frame, ds) for ds in DOWNSCALES]:
             f.result()
@@ -230,6 +256,20 @@ def main():
         fr.release()
     blends_per_step = sum(stats[ds]["n_blends"] for ds in DOWNSCALES)
 
+    if args.traffic_probe:
+        # the counters of this run give the HBM bytes of every kernel of one
+        # step; the elementwise product below moves exactly 1 GiB in and 1 GiB
+        # out and calibrates FETCH_SIZE / WRITE_SIZE
+        args.serial = True
+        step()
+        torch.cuda.synchronize()
+        x = torch.ones(1 << 28, device="cuda")
+        y = torch.empty_like(x)
+        torch.mul(x, 2.0, out=y)
+        torch.cuda.synchronize()
+        print("bench: traffic probe done", file=sys.stderr, flush=True)
+        return
+
     print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -242,45 +282,69 @@ def main():
     dt = time.perf_counter() - t0
     ms_per_step = dt / args.steps * 1e3
     pool.shutdown()
+    # kernel timing: the same steps with the frames one after another, so that
+    # a kernel's launch time is its own and not shared with another frame's
+    print("bench: kernel-timing steps", file=sys.stderr, flush=True)
+    for _ in range(args.steps):
+        step(prof=True)
+    torch.cuda.synchronize()
 
-    # live per-stage device time over the timed configuration (profiled steps)
-    prof_steps = max(3, min(args.steps, 10))
-    stage_tot = {s: 0.0 for s in STAGES}
-    per_ds_stage = {ds: {s: 0.0 for s in STAGES} for ds in DOWNSCALES}
-    for _ in range(prof_steps):
-        for ds in DOWNSCALES:
-            _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, profile=True)
-            M.render_backward(ctx, fr, dls[ds])
-            st = fr.stats()
-            fr.release()
-            for i, s in enumerate(STAGES):
-                per_ds_stage[ds][s] += st["stage_us"][i] / prof_steps
-                stage_tot[s] += st["stage_us"][i] / prof_steps
+    per_ds_stage = {ds: {s: v / args.steps for s, v in stage_acc[ds].items()} for ds in DOWNSCALES}
+    stage_tot = {s: sum(per_ds_stage[ds][s] for ds in DOWNSCALES) for s in STAGES}
     dominant = max(STAGES, key=lambda s: stage_tot[s])
-
-    # roofline of the dominant stage at its largest launch (the 1x frame)
-    st1 = stats[1]
-    us = per_ds_stage[1][dominant]
     print("bench: stage us per step " + json.dumps({k: round(v, 1) for k, v in stage_tot.items()}),
           file=sys.stderr, flush=True)
-    if dominant in ("blend", "blend_bwd"):
-        flops = FLOPS_PER_VISIT * st1["n_visits"] + FLOPS_PER_BLEND * st1["n_blends"]
-        achieved = flops / (us * 1e-6) / 1e12
-        roof = {"bound": "alu", "kernel": "k_blend" if dominant == "blend" else "k_blend_bwd",
-                "launch": "1x frame, selective", "achieved": achieved, "peak": ALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / ALU_PEAK_TFLOPS,
-                "algorithmic": f"{flops} flops = {FLOPS_PER_VISIT} x {st1['n_visits']} visits + "
-                               f"{FLOPS_PER_BLEND} x {st1['n_blends']} blends",
-                "avg_launch_us": us,
-                "traffic": traffic_for("k_blend" if dominant == "blend" else "k_blend_bwd", "1x")}
+
+    # algorithmic work of every stage at every downscale
+    def stage_work(ds):
+        st = stats[ds]
+        bits = max(1, int(np.ceil(np.log2(max(2, st["tiles_x"] * st["tiles_y"])))))
+        b = stage_bytes(st, sc.n, sc.sh_degree, 4, (bits + 7) // 8)
+        b["blend"] = FLOPS_PER_VISIT * st["n_visits"] + FLOPS_PER_BLEND * st["n_blends"]
+        b["blend_bwd"] = (FLOPS_PER_VISIT * st["n_visits"] +
+                          FLOPS_PER_BLEND_BWD * st["n_blends"])
+        return b
+
+    work = {ds: stage_work(ds) for ds in DOWNSCALES}
+    # roofline of the dominant kernel over all its launches of a step: total
+    # algorithmic work / total launch time (= per-launch average over the four
+    # frames, the figure a kernel-trace summary of the same run reports)
+    tot_us = stage_tot[dominant]
+    tot_work = sum(work[ds][dominant] for ds in DOWNSCALES)
+    launches = len(DOWNSCALES)
+    alu = dominant in ("blend", "blend_bwd")
+    kname = {"blend": "k_blend", "blend_bwd": "k_blend_bwd"}.get(dominant, dominant)
+    if alu:
+        achieved = tot_work / (tot_us * 1e-6) / 1e12
+        per = (f"fwd: {FLOPS_PER_VISIT} flops/visit + {FLOPS_PER_BLEND} flops/blend" if dominant == "blend"
+               else f"bwd: {FLOPS_PER_VISIT} flops/visit + {FLOPS_PER_BLEND_BWD} flops/blend")
+        roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / ALU_PEAK_TFLOPS}
     else:
-        ntile_bits = max(1, int(np.ceil(np.log2(max(2, st1["tiles_x"] * st1["tiles_y"])))))
-        b = stage_bytes(st1, sc.n, sc.sh_degree, 4, (ntile_bits + 7) // 8)[dominant]
-        achieved = b / (us * 1e-6) / 1e9
-        roof = {"bound": "hbm", "kernel": dominant, "launch": "1x frame, selective",
-                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "algorithmic": f"{b} bytes",
-                "avg_launch_us": us, "traffic": traffic_for(dominant, "1x")}
+        achieved = tot_work / (tot_us * 1e-6) / 1e9
+        per = "bytes as listed in stage_bytes()"
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS}
+    roof.update({
+        "kernel": kname, "launches_per_step": launches,
+        "avg_launch_us": tot_us / launches,
+        "algorithmic_per_launch": tot_work / launches,
+        "algorithmic": per + "; visits/blends per launch averaged over the 1x, 4x, 16x, 64x frames",
+        "frac_1x_launch": ((work[1][dominant] / (per_ds_stage[1][dominant] * 1e-6)) /
+                           ((ALU_PEAK_TFLOPS * 1e12) if alu else (HBM_PEAK_GBS * 1e9))),
+        "measured": "HIP events on the frame's stream around each stage, averaged over "
+                    f"{args.steps} steps run frame after frame after the timed region",
+        "traffic": traffic_for(kname, "avg")})
+    # HBM-bound stages: achieved algorithmic bandwidth per downscale
+    hbm_stages = {}
+    for s in ("project", "depth_sort", "count_scan", "emit", "tile_sort", "ranges", "zero_bwd",
+              "chain_bwd"):
+        hbm_stages[s] = {}
+        for ds in DOWNSCALES:
+            us = per_ds_stage[ds][s]
+            gbs = work[ds][s] / (us * 1e-6) / 1e9 if us > 0 else 0.0
+            hbm_stages[s][str(ds)] = {"us": round(us, 2), "bytes": int(work[ds][s]),
+                                      "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
     # per-downscale frame rate and latency, selective vs single-scale (forward)
     per_ds = {}
@@ -328,6 +392,7 @@ def main():
                    "blends_per_step": blends_per_step},
         "roofline": roof,
         "stage_us_per_step": {s: round(v, 2) for s, v in stage_tot.items()},
+        "hbm_stages": hbm_stages,
         "per_downscale": per_ds,
     }
     if not args.no_serving:

@@ -130,8 +130,9 @@ typedef struct {
    * [0] projection + selection + compaction  [1] depth sort  [2] tile-count scan
    * [3] emission  [4] tile sort  [5] tile ranges  [6] blending
    * [7] backward blend replay  [8] backward per-Gaussian sum + chain rule
-   * [9] whole forward (first to last stage, excluding the host wait) */
-  float stage_us[10];
+   * [9] whole forward (first to last stage, excluding the host wait)
+   * [10] backward: zeroing of the per-instance partials  [11] whole backward */
+  float stage_us[12];
 } msgs_stats;
 
 /* Gradient outputs, caller-owned device planar buffers with the scene's

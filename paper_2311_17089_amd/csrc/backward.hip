@@ -422,12 +422,17 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+void launch_backward_zero(const BwdArgs& a, hipStream_t st) {
+  if (a.n_inst > 0) {
+    const int64_t m = 3 * a.n_inst;
+    hipLaunchKernelGGL(k_fill_f4, dim3(grid_for(m)), dim3(kBlock), 0, st, (float4*)a.partial, m);
+  }
+}
+
 void launch_backward_blend(const BwdArgs& a, hipStream_t st) {
   const int ntile = a.v.Tx * a.v.Ty;
   const int nblk = (ntile + 31) / 32 * 32;
   if (a.n_inst > 0) {
-    const int64_t m = 3 * a.n_inst;
-    hipLaunchKernelGGL(k_fill_f4, dim3(grid_for(m)), dim3(kBlock), 0, st, (float4*)a.partial, m);
     hipLaunchKernelGGL(k_blend_bwd, dim3(nblk), dim3(kBlock), 0, st, a.ranges, a.tvals, a.rec,
                        a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last, a.dL_drgb, a.partial);
   }

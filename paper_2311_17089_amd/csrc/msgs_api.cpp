@@ -496,6 +496,8 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
     launch_fill_u32(a.nbig, 1, 0u, st);
     msgs_frame* fm = const_cast<msgs_frame*>(f);
     if (fm->profile) (void)hipEventRecord(fm->ev[9], st);
+    launch_backward_zero(a, st);
+    if (fm->profile) (void)hipEventRecord(fm->ev[12], st);
     launch_backward_blend(a, st);
     if (fm->profile) (void)hipEventRecord(fm->ev[10], st);
     launch_backward_chain(a, st);
@@ -532,7 +534,7 @@ int msgs_frame_stats(const msgs_frame* f, msgs_stats* out) {
   unsigned long long h[6];
   hipError_t e = hipMemcpy(h, f->ctr, sizeof h, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "stats readback");
-  for (int i = 0; i < 10; ++i) out->stage_us[i] = 0.0f;
+  for (int i = 0; i < 12; ++i) out->stage_us[i] = 0.0f;
   if (f->profile) {
     auto span = [&](int a, int b) {
       float ms = 0.0f;
@@ -552,8 +554,10 @@ int msgs_frame_stats(const msgs_frame* f, msgs_stats* out) {
     out->stage_us[9] = span(0, 3) + span(4, 8);
     if (f->bwd_recorded) {
       (void)hipEventSynchronize(f->ev[11]);
-      out->stage_us[7] = span(9, 10);
+      out->stage_us[7] = span(12, 10);
       out->stage_us[8] = span(10, 11);
+      out->stage_us[10] = span(9, 12);
+      out->stage_us[11] = span(9, 11);
     }
   }
   out->n_visits = (int64_t)h[4];

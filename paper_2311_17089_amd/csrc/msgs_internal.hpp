@@ -67,7 +67,7 @@ struct msgs_frame {
   std::vector<void*> blocks;          // allocations owned by the frame
   // profiling events (opts.profile): forward stage boundaries 0..8, backward 9..11
   bool profile = false;
-  hipEvent_t ev[12] = {};
+  hipEvent_t ev[13] = {};
   bool bwd_recorded = false;
   // kept for the backward pass and the getters
   unsigned long long* ctr = nullptr;   // [0] selected [1] blends [2] visible [3] instances [4] visits [5] evaluations

@@ -49,7 +49,7 @@ class Stats(C.Structure):
                 ("n_instances", C.c_int64), ("n_blends", C.c_int64), ("n_visits", C.c_int64),
                 ("n_evals", C.c_int64),
                 ("width", C.c_int), ("height", C.c_int), ("tiles_x", C.c_int), ("tiles_y", C.c_int),
-                ("stage_us", C.c_float * 10)]
+                ("stage_us", C.c_float * 12)]
 
 
 class Grads(C.Structure):
