@@ -37,15 +37,37 @@ __device__ __forceinline__ void st_status(unsigned long long* p, unsigned long l
 }
 
 // Exclusive prefix of the values published by the tickets before `t` for one
-// column of the status table (row stride `stride`).
+// column of the status table (row stride `stride`).  The status words of up to
+// kWindow predecessors are read at once (independent loads), so a walk over
+// many published aggregates costs one memory latency per kWindow tickets.  A
+// word that is not ready yet is polled again from that ticket on.
+template <int kWindow = 8>
 __device__ __forceinline__ unsigned long long look_back(const unsigned long long* status,
                                                         int64_t stride, int64_t t) {
   unsigned long long excl = 0;
-  for (int64_t p = t - 1; p >= 0; --p) {
-    unsigned long long s;
-    while (((s = ld_status(status + p * stride)) >> 62) == 0) __builtin_amdgcn_s_sleep(1);
-    excl += s & kValMask;
-    if ((s >> 62) == 2) break;
+  int64_t p = t - 1;
+  while (p >= 0) {
+    unsigned long long s[kWindow];
+#pragma unroll
+    for (int w = 0; w < kWindow; ++w) s[w] = p - w >= 0 ? ld_status(status + (p - w) * stride) : 0ull;
+    int w = 0;
+    bool done = false;
+    for (; w < kWindow; ++w) {
+      if (p - w < 0) {
+        done = true;
+        break;
+      }
+      const unsigned long long f = s[w] >> 62;
+      if (f == 0) break;
+      excl += s[w] & kValMask;
+      if (f == 2) {
+        done = true;
+        break;
+      }
+    }
+    if (done) break;
+    p -= w;
+    if (w < kWindow) __builtin_amdgcn_s_sleep(6);
   }
   return excl;
 }
@@ -145,12 +167,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_lb(const uint32_t* in, const ui
 }
 
 // ------------------------------------------------------------------ radix sort
-// Digit histograms of every pass, one read of the keys: workgroup b counts a
-// contiguous chunk into its own row of rows[pass][b][digit] (no global atomics).
+// Digit histograms of every pass, one read of the keys: each workgroup counts
+// a contiguous chunk in LDS (one sub-histogram per wave) and adds its counts to
+// the global histogram hist[pass][digit] with one atomic per (pass, digit).
 constexpr int kHistBlocks = 256;
+constexpr int kHistUnroll = 8;
 __global__ __launch_bounds__(kBlock) void k_os_hist(const uint32_t* keys, const uint32_t* d_n,
                                                     int64_t nmax, int begin_bit, int end_bit,
-                                                    uint32_t* rows) {
+                                                    uint32_t* hist) {
   __shared__ uint32_t h[4][kBlock / 64][kRadix];
   const int wave = threadIdx.x >> 6;
   const int npass = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
@@ -161,12 +185,22 @@ __global__ __launch_bounds__(kBlock) void k_os_hist(const uint32_t* keys, const 
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * chunk;
   const int64_t i1 = min(n, i0 + chunk);
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
-    const uint32_t key = keys[i];
-    for (int p = 0; p < npass; ++p) {
-      const int sh = begin_bit + p * kRadixBits;
-      const int nb = min(kRadixBits, end_bit - sh);
-      atomicAdd(&h[p][wave][(key >> sh) & ((1u << nb) - 1u)], 1u);
+  for (int64_t b = i0; b < i1; b += (int64_t)kBlock * kHistUnroll) {
+    uint32_t kk[kHistUnroll];
+#pragma unroll
+    for (int u = 0; u < kHistUnroll; ++u) {
+      const int64_t i = b + u * kBlock + threadIdx.x;
+      kk[u] = i < i1 ? keys[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kHistUnroll; ++u) {
+      if (b + u * kBlock + threadIdx.x < i1) {
+        for (int p = 0; p < npass; ++p) {
+          const int sh = begin_bit + p * kRadixBits;
+          const int nb = min(kRadixBits, end_bit - sh);
+          atomicAdd(&h[p][wave][(kk[u] >> sh) & ((1u << nb) - 1u)], 1u);
+        }
+      }
     }
   }
   __syncthreads();
@@ -174,28 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_os_hist(const uint32_t* keys, const 
     uint32_t c = 0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) c += h[p][w][threadIdx.x];
-    rows[((int64_t)p * gridDim.x + blockIdx.x) * kRadix + threadIdx.x] = c;
-  }
-}
-
-// Digit totals of each pass (sum over the histogram rows), exclusive-scanned
-// into the global start of every digit (one workgroup).
-__global__ __launch_bounds__(kBlock) void k_os_hist_scan(const uint32_t* rows, int nrows,
-                                                         uint32_t* gstart, int npass) {
-  __shared__ uint32_t wtot[kBlock / 64];
-  for (int p = 0; p < npass; ++p) {
-    const uint32_t* rp = rows + (int64_t)p * nrows * kRadix + threadIdx.x;
-    uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int r = 0;
-    for (; r + 8 <= nrows; r += 8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] += rp[(int64_t)(r + u) * kRadix];
-    }
-    for (; r < nrows; ++r) acc[0] += rp[(int64_t)r * kRadix];
-    const uint32_t v = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan(v, wtot, tot);
-    gstart[p * kRadix + threadIdx.x] = ex;
+    if (c) atomicAdd(&hist[p * kRadix + threadIdx.x], c);
   }
 }
 
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
                                                     const uint32_t* vals_in, uint32_t* keys_out,
                                                     uint32_t* vals_out, const uint32_t* d_n,
                                                     int64_t nmax, int shift, int nbits,
-                                                    const uint32_t* gstart,
+                                                    const uint32_t* hist,
                                                     unsigned long long* status,
                                                     uint32_t* ticket) {
   constexpr int TILE = kBlock * ITEMS;
@@ -213,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   __shared__ uint32_t gdig[kRadix];
   __shared__ uint32_t wtot[kBlock / 64];
   __shared__ uint32_t ks[TILE];
-  __shared__ uint32_t vs[TILE];
+  __shared__ uint8_t sdig[TILE];
   __shared__ int64_t s_tile;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
@@ -225,29 +238,43 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   const int64_t tbase = t * TILE;
   const int64_t wbase = tbase + (int64_t)wave * (64 * ITEMS);
   const uint32_t mask = (1u << nbits) - 1u;
-  const unsigned long long lt = __lanemask_lt();
-  uint32_t k_[ITEMS], v_[ITEMS], r_[ITEMS];
+  // number of valid items of this wave's slice (32-bit offsets from here on)
+  const int64_t wrem = n - wbase;
+  const int remw = wrem <= 0 ? 0 : (wrem >= 64 * ITEMS ? 64 * ITEMS : (int)wrem);
+  const uint32_t* kin_w = keys_in + (wrem > 0 ? wbase : 0);
+  const uint32_t* vin_w = vals_in + (wrem > 0 ? wbase : 0);
+  uint32_t k_[ITEMS], r_[ITEMS];
+  // all key loads of the tile are issued before any ranking
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) k_[i] = i * 64 + lane < remw ? kin_w[i * 64 + lane] : 0u;
+  // global start of every digit: exclusive scan of the digit totals
+  uint32_t htot;
+  const uint32_t gs = block_excl_scan(hist[threadIdx.x], wtot, htot);
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const int64_t idx = wbase + i * 64 + lane;
-    const bool valid = idx < n;
-    const uint32_t key = valid ? keys_in[idx] : 0u;
-    k_[i] = key;
-    v_[i] = valid ? vals_in[idx] : 0u;
-    const uint32_t d = (key >> shift) & mask;
-    unsigned long long m = __ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const unsigned long long bb = __ballot(bit);
-      m &= bit ? bb : ~bb;
+    const bool valid = i * 64 + lane < remw;
+    const uint32_t d = (k_[i] >> shift) & mask;
+    // lanes holding the same digit: AND over the digit's bits of the ballot of
+    // that bit or of its complement (the bits of d at and above nbits are 0)
+    const unsigned long long vm = __ballot(valid);
+    uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const uint32_t sb = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // 0 or ~0
+      const unsigned long long bb = __ballot(sb != 0u);
+      mlo &= ~((uint32_t)bb ^ sb);
+      mhi &= ~((uint32_t)(bb >> 32) ^ sb);
     }
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
     uint32_t before = 0;
     if (valid) before = cnt[wave][d];
-    r_[i] = before + (uint32_t)__popcll(m & lt);
-    if (valid && lane == __ffsll((long long)m) - 1) cnt[wave][d] = before + (uint32_t)__popcll(m);
+    r_[i] = before + below;
+    // the lowest lane of each digit group advances the wave's digit counter
+    if (valid && below == 0u) cnt[wave][d] = before + (uint32_t)(__popc(mlo) + __popc(mhi));
   }
   __syncthreads();
-  // per digit: cross-wave prefix, tile count, local digit start
+  // per digit: cross-wave prefix, tile count, local digit start; the tile's
+  // count is published before anything else
   const int d = threadIdx.x;
   uint32_t bt = 0;
 #pragma unroll
@@ -256,39 +283,54 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
     cnt[w][d] = bt;
     bt += c;
   }
+  unsigned long long* st = status + t * kRadix + d;
+  st_status(st, (t == 0 ? kFlagP : kFlagA) | bt);
   uint32_t tot;
   ldig[d] = block_excl_scan(bt, wtot, tot);
-  unsigned long long* st = status + t * kRadix + d;
-  unsigned long long excl = 0;
-  if (t == 0) {
-    st_status(st, kFlagP | bt);
-  } else {
-    st_status(st, kFlagA | bt);
-    excl = look_back(status + d, kRadix, t);
-    st_status(st, kFlagP | (excl + bt));
-  }
-  gdig[d] = gstart[d] + (uint32_t)excl;
   __syncthreads();
-  // reorder the tile by digit in LDS
+  // keys (and their digits) to their place in the digit-ordered tile in LDS
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
-    const int64_t idx = wbase + i * 64 + lane;
-    if (idx < n) {
-      const uint32_t dd = (k_[i] >> shift) & mask;
-      const uint32_t lp = ldig[dd] + cnt[wave][dd] + r_[i];
-      ks[lp] = k_[i];
-      vs[lp] = v_[i];
+    const uint32_t dd = (k_[i] >> shift) & mask;
+    r_[i] += ldig[dd] + cnt[wave][dd];
+    if (i * 64 + lane < remw) {
+      ks[r_[i]] = k_[i];
+      sdig[r_[i]] = (uint8_t)dd;
     }
   }
+  // the values are loaded while the look-back runs
+  uint32_t v_[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) v_[i] = i * 64 + lane < remw ? vin_w[i * 64 + lane] : 0u;
+  unsigned long long excl = 0;
+  if (t > 0) {
+    excl = look_back<4>(status + d, kRadix, t);
+    st_status(st, kFlagP | (excl + bt));
+  }
+  gdig[d] = gs + (uint32_t)excl;
   __syncthreads();
   const int64_t rem = n - tbase;
   const int cntile = rem <= 0 ? 0 : (rem >= TILE ? TILE : (int)rem);
-  for (int p = threadIdx.x; p < cntile; p += kBlock) {
-    const uint32_t key = ks[p];
-    const uint32_t dd = (key >> shift) & mask;
-    const uint32_t g = gdig[dd] + ((uint32_t)p - ldig[dd]);
-    keys_out[g] = key;
-    vals_out[g] = vs[p];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int p = i * kBlock + threadIdx.x;
+    if (p < cntile) {
+      const uint32_t dd = sdig[p];
+      keys_out[gdig[dd] + ((uint32_t)p - ldig[dd])] = ks[p];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i)
+    if (i * 64 + lane < remw) ks[r_[i]] = v_[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int p = i * kBlock + threadIdx.x;
+    if (p < cntile) {
+      const uint32_t dd = sdig[p];
+      vals_out[gdig[dd] + ((uint32_t)p - ldig[dd])] = ks[p];
+    }
   }
 }
 
@@ -316,8 +358,7 @@ void scan_excl_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, co
 size_t radix_tmp_bytes(int64_t nmax, int npass) {
   const int items = sort_items(nmax);
   const int64_t nblk = (nmax + kBlock * items - 1) / (kBlock * items);
-  return (size_t)npass * kRadix * 4 + (size_t)npass * (nblk > 0 ? nblk : 1) * kRadix * 8 + 64 * 4 +
-         (size_t)npass * kHistBlocks * kRadix * 4;
+  return (size_t)npass * kRadix * 4 + (size_t)npass * (nblk > 0 ? nblk : 1) * kRadix * 8 + 64 * 4;
 }
 
 int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
@@ -331,13 +372,11 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
   uint32_t* ghist = (uint32_t*)tmp;
   unsigned long long* status = (unsigned long long*)(ghist + npass * kRadix);
   uint32_t* tickets = (uint32_t*)(status + npass * nblk * kRadix);
-  uint32_t* rows = tickets + 64;
   const int64_t zero_words = npass * kRadix + 2 * npass * nblk * kRadix + 64;
   launch_fill_u32((uint32_t*)tmp, zero_words, 0u, st);
   const int hgrid = (int)std::min<int64_t>((nmax + 4095) / 4096, kHistBlocks);
   hipLaunchKernelGGL(k_os_hist, dim3(hgrid), dim3(kBlock), 0, st, keys, d_n, nmax, begin_bit,
-                     end_bit, rows);
-  hipLaunchKernelGGL(k_os_hist_scan, dim3(1), dim3(kBlock), 0, st, rows, hgrid, ghist, npass);
+                     end_bit, ghist);
   uint32_t* kin = keys;
   uint32_t* vin = vals;
   uint32_t* kout = keys_alt;
