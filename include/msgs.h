@@ -123,8 +123,10 @@ typedef struct {
   int64_t n_blends;     /* accumulated contributions over all pixels */
   int64_t n_visits;     /* (pixel, instance) pairs up to each pixel's stop position in
                            its tile list (the work of plain tile compositing) */
-  int64_t n_evals;      /* (pixel, instance) pairs whose Gaussian was evaluated after
-                           the per-quadrant footprint cull */
+  int64_t n_evals;      /* (pixel, instance) evaluations the compositing waves spent:
+                           per 8x8 quadrant, the list entries that passed its
+                           footprint cull up to the point where all its pixels had
+                           stopped, times its pixels inside the frame */
   int width, height, tiles_x, tiles_y;
   /* device time (us) per stage when rendered with profile = 1, else 0:
    * [0] projection + selection + compaction  [1] depth sort  [2] tile-count scan

@@ -26,7 +26,7 @@ template <int D>
 __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, uint8_t* sel_out,
                                                     uint32_t* count, uint32_t* depthkey,
                                                     Rec* rec, uint2* rect, uint32_t* blk_vis,
-                                                    unsigned long long* n_sel_ctr) {
+                                                    unsigned long long* slots) {
   const int64_t n = s.n;
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   uint32_t ntiles = 0;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, u
   int cs = __syncthreads_count(selected);
   if (threadIdx.x == 0) {
     blk_vis[blockIdx.x] = (uint32_t)c;
-    if (cs) atomicAdd(n_sel_ctr, (unsigned long long)cs);
+    if (cs) atomicAdd(&slots[(blockIdx.x % kCtrSlots) * 4 + 0], (unsigned long long)cs);
   }
 }
 
@@ -212,27 +212,36 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
   return (((c >> 2) << 3) + (b & 7)) * 4 + (c & 3);
 }
 
-// One workgroup per tile, four independent waves: wave w owns the 8x8
-// quadrant w of the tile and walks the tile's list on its own, 64 instances
-// at a time.  Each lane gathers one record; a ballot keeps the instances whose
+// XCD-aware map of a one-wave workgroup to (tile, 8x8 quadrant): the four
+// quadrants of a tile are consecutive workgroups of one XCD, and each XCD
+// takes groups of four neighbouring tiles as xcd_tile does.
+__device__ __forceinline__ int xcd_quad(int b, int& quad) {
+  const int c = b >> 3;  // index of the workgroup within its XCD
+  quad = c & 3;
+  const int cc = c >> 2;
+  return (((cc >> 2) << 3) + (b & 7)) * 4 + (cc & 3);
+}
+
+// One single-wave workgroup per 8x8 quadrant of a 16x16 tile: the wave walks
+// the tile's list on its own, 64 instances at a time (a finished quadrant
+// frees its slot at once, whatever the rest of the tile does).  Each lane gathers one record; a ballot keeps the instances whose
 // level-set box reaches the quadrant and the survivors are packed, in order,
 // into the wave's LDS buffer; then every lane (pixel) composites them.  The
 // next chunk's gathers are in flight meanwhile.  No workgroup barrier: a wave
 // stops as soon as its own 64 pixels are done.
-__global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uint32_t* tvals,
+__global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_t* tvals,
                                                   const Rec* rec, ViewParams v, int ntile,
                                                   float* rgb, float* T_final, uint32_t* n_accum,
                                                   uint32_t* n_last,
-                                                  unsigned long long* blend_ctr,
-                                                  unsigned long long* visit_ctr,
-                                                  unsigned long long* eval_ctr) {
-  __shared__ float4 s0[4][64], s1[4][64], s2[4][64];
-  __shared__ uint32_t spos[4][64];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+                                                  unsigned long long* slots) {
+  __shared__ float4 s0[64], s1[64], s2[64];
+  __shared__ uint32_t spos[64];
+  int quad;
+  const int tile = xcd_quad(blockIdx.x, quad);
   if (tile >= ntile) return;
   const int tx = tile % v.Tx, ty = tile / v.Tx;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int qx = tx * kTile + (wave & 1) * 8, qy = ty * kTile + (wave >> 1) * 8;
+  const int lane = threadIdx.x;
+  const int qx = tx * kTile + (quad & 1) * 8, qy = ty * kTile + (quad >> 1) * 8;
   const int px = qx + (lane & 7);
   const int py = qy + (lane >> 3);
   const bool inside = px < v.W && py < v.H;
@@ -243,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
   const uint2 rg = ranges[tile];
   float T = 1.0f;
   float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  uint32_t cnt = 0, last = 0, evals = 0;
+  uint32_t cnt = 0, last = 0, wev = 0;
   uint32_t visits = inside ? rg.y - rg.x : 0u;  // replaced by the stop position on termination
   bool done = !inside;
   const unsigned long long lt = __lanemask_lt();
@@ -264,10 +273,20 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
     const int nl = __popcll(m);
     if (hit) {
       const int q = __popcll(m & lt);
-      s0[wave][q] = n0;
-      s1[wave][q] = n1;
-      s2[wave][q] = n2;
-      spos[wave][q] = c0 - rg.x + (uint32_t)lane + 1;
+      s0[q] = n0;
+      s1[q] = n1;
+      s2[q] = n2;
+      spos[q] = c0 - rg.x + (uint32_t)lane + 1;
+    }
+    // the compositing below reads up to three entries past the last hit and
+    // masks them out by multiplying with zero, so those entries must hold
+    // finite values (LDS keeps whatever an earlier workgroup left there)
+    if (lane >= nl && lane < nl + 3) {
+      const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      s0[lane] = z;
+      s1[lane] = z;
+      s2[lane] = z;
+      spos[lane] = 0u;
     }
     const uint32_t nidx = c0 + 64 + lane;
     have = nidx < rg.y;
@@ -280,7 +299,8 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
     // branch-free compositing, four instances per step: evaluated
     // independently, composited in order with selects; a lane that is done
     // adds exactly zero (C + c * 0 = C, T unchanged)
-    for (int i = 0; i < nl; i += 4) {
+    int i = 0;
+    for (; i < nl; i += 4) {
       float ar[4];
       bool pre[4];
       float4 cb[4];
@@ -288,8 +308,8 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = min(i + u, 63);
-        const float4 a = s0[wave][j];
-        const float4 b = s1[wave][j];
+        const float4 a = s0[j];
+        const float4 b = s1[j];
         const float dx = pcx - a.x;
         const float dy = pcy - a.y;
         const float qxx = dx * dx, qyy = dy * dy, qxy = dx * dy;
@@ -297,8 +317,8 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
         const float power = e - a.w * qxy;
         ar[u] = b.y * exp_c(power);
         pre[u] = (i + u < nl) && !(power > 0.0f) && !(power < b.z) && !(ar[u] < kAlphaMin);
-        cb[u] = make_float4(b.w, s2[wave][j].x, s2[wave][j].y, 0.0f);
-        p1[u] = spos[wave][j];
+        cb[u] = make_float4(b.w, s2[j].x, s2[j].y, 0.0f);
+        p1[u] = spos[j];
       }
       bool any_stop = false;
 #pragma unroll
@@ -314,14 +334,17 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
         C2 = C2 + cb[u].z * w;
         T = acc ? Tn : T;
         cnt += acc ? 1u : 0u;
-        evals += (i + u < nl && !done) ? 1u : 0u;
         last = acc ? p1[u] : last;
         visits = stop ? p1[u] : visits;
         done = done || stop;
         any_stop = any_stop || stop;
       }
-      if (__any(any_stop) && __all(done)) break;  // both votes are wave-uniform
+      if (__any(any_stop) && __all(done)) {  // both votes are wave-uniform
+        i += 4;
+        break;
+      }
     }
+    wev += (uint32_t)min(i, nl);
   }
   if (inside) {
     const int64_t pix = (int64_t)py * v.W + px;
@@ -332,17 +355,46 @@ __global__ __launch_bounds__(kBlock) void k_blend(const uint2* ranges, const uin
     n_accum[pix] = cnt;
     n_last[pix] = last;
   }
-  // per-wave counts (one atomic per wave)
-  unsigned long long c64 = cnt, v64 = visits, e64 = evals;
+  // per-wave counts, added to one of kCtrSlots counter slots (atomics on a
+  // single address from every wave would serialise at the memory side)
+  unsigned long long c64 = cnt, v64 = visits;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     c64 += __shfl_xor(c64, o, 64);
     v64 += __shfl_xor(v64, o, 64);
-    e64 += __shfl_xor(e64, o, 64);
   }
-  if (lane == 0 && c64) atomicAdd(blend_ctr, c64);
-  if (lane == 0 && v64) atomicAdd(visit_ctr, v64);
-  if (lane == 0 && e64) atomicAdd(eval_ctr, e64);
+  const unsigned long long e64 =
+      (unsigned long long)wev * (unsigned long long)__popcll(__ballot(inside));
+  unsigned long long* sl = slots + (blockIdx.x % kCtrSlots) * 4;
+  if (lane == 0 && c64) atomicAdd(sl + 1, c64);
+  if (lane == 0 && v64) atomicAdd(sl + 2, v64);
+  if (lane == 0 && e64) atomicAdd(sl + 3, e64);
+}
+
+// Totals of the counter slots: ctr[0] selected, ctr[1] blends, ctr[4] visits,
+// ctr[5] evaluations (fixed summation order).
+__global__ __launch_bounds__(kCtrSlots) void k_sum_slots(const unsigned long long* slots,
+                                                         unsigned long long* ctr) {
+  __shared__ unsigned long long part[4][kCtrSlots / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    unsigned long long x = slots[threadIdx.x * 4 + q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) part[q][wave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kCtrSlots / 64; ++w) t += part[threadIdx.x][w];
+    const int dst[4] = {0, 1, 4, 5};
+    ctr[dst[threadIdx.x]] = t;
+  }
+}
+
+void launch_sum_slots(const unsigned long long* slots, unsigned long long* ctr, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(kCtrSlots), 0, st, slots, ctr);
 }
 
 __global__ __launch_bounds__(kBlock) void k_debug_exp(const float* x, float* y, int64_t n) {
@@ -360,14 +412,14 @@ static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) 
 
 void launch_project(const SceneView& s, const ViewParams& v, uint8_t* sel, uint32_t* count,
                     uint32_t* depthkey, Rec* rec, uint2* rect, uint32_t* blk_vis,
-                    unsigned long long* n_sel_ctr, hipStream_t st) {
+                    unsigned long long* slots, hipStream_t st) {
   if (s.n == 0) return;
   const dim3 g(grid_for(s.n)), b(kBlock);
   switch (s.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project<0>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, n_sel_ctr); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, n_sel_ctr); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, n_sel_ctr); break;
-    default: hipLaunchKernelGGL(k_project<3>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, n_sel_ctr); break;
+    case 0: hipLaunchKernelGGL(k_project<0>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, slots); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, slots); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, slots); break;
+    default: hipLaunchKernelGGL(k_project<3>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, slots); break;
   }
 }
 
@@ -398,12 +450,11 @@ void launch_ranges(const uint32_t* tkeys, uint32_t ninst, uint2* ranges, hipStre
 
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* blend_ctr, unsigned long long* visit_ctr,
-                  unsigned long long* eval_ctr, hipStream_t st) {
+                  unsigned long long* slots, hipStream_t st) {
   const int ntile = v.Tx * v.Ty;
-  const int nblk = (ntile + 31) / 32 * 32;
-  hipLaunchKernelGGL(k_blend, dim3(nblk), dim3(kBlock), 0, st, ranges, tvals, rec, v, ntile, rgb,
-                     T_final, n_accum, n_last, blend_ctr, visit_ctr, eval_ctr);
+  const int nblk = (ntile + 31) / 32 * 32 * 4;
+  hipLaunchKernelGGL(k_blend, dim3(nblk), dim3(64), 0, st, ranges, tvals, rec, v, ntile, rgb,
+                     T_final, n_accum, n_last, slots);
 }
 
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st) {

@@ -126,7 +126,7 @@ int render_phase1(msgs_frame* f) {
   const bool even = radix_passes(0, 32) % 2 == 0;
   uint32_t* dv0 = nullptr;
   Carve keep;
-  keep.add(&f->ctr, 8 * sizeof(unsigned long long));
+  keep.add(&f->ctr, (8 + 4 * kCtrSlots) * sizeof(unsigned long long));
   keep.add(&f->sel, n);
   keep.add(&f->count, n * 4);
   keep.add(&f->depthkey, n * 4);
@@ -156,10 +156,10 @@ int render_phase1(msgs_frame* f) {
   uint32_t* vin = even ? f->order : f->dvals_alt;
   uint32_t* valt = even ? f->dvals_alt : f->order;
   dv0 = vin;
-  launch_fill_u32((uint32_t*)f->ctr, 16, 0u, st);
+  launch_fill_u32((uint32_t*)f->ctr, 2 * (8 + 4 * kCtrSlots), 0u, st);
   mark(f, 0);
   launch_project(f->scene->view, v, f->sel, f->count, f->depthkey, f->rec, f->rect, f->blk_vis,
-                 &f->ctr[0], st);
+                 f->ctr + 8, st);
   scan_excl_u32(f->blk_vis, nullptr, f->blk_off, nullptr, nb, &f->ctr[2], f->scan_tmp, st);
   launch_compact(f->count, f->depthkey, n, f->blk_off, f->dkeys[0], dv0, st);
   mark(f, 1);
@@ -211,8 +211,9 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   launch_ranges(f->tkeys, (uint32_t)I, f->ranges, st);
   mark(f, 7);
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
-               &f->ctr[1], &f->ctr[4], &f->ctr[5], st);
+               f->ctr + 8, st);
   mark(f, 8);
+  launch_sum_slots(f->ctr + 8, f->ctr, st);
   f->ctx->cache.free(f->ctx, tmp.base, st);
   f->ctx->cache.free(f->ctx, f->tmp_block, st);
   f->tmp_block = nullptr;

@@ -13,6 +13,9 @@
 
 namespace msgs {
 
+// counter slots per frame (spread per-block/per-wave counter atomics)
+constexpr int kCtrSlots = 256;
+
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
 constexpr int kTile = 16;     // tile edge in pixels (Sec. 3.1)
 

@@ -12,7 +12,7 @@ namespace msgs {
 // forward.hip
 void launch_project(const SceneView& s, const ViewParams& v, uint8_t* sel, uint32_t* count,
                     uint32_t* depthkey, Rec* rec, uint2* rect, uint32_t* blk_vis,
-                    unsigned long long* n_sel_ctr, hipStream_t st);
+                    unsigned long long* slots, hipStream_t st);
 void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
                     const uint32_t* blk_off, uint32_t* keys, uint32_t* vals, hipStream_t st);
 void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_nvis,
@@ -22,8 +22,8 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 void launch_ranges(const uint32_t* tkeys, uint32_t ninst, uint2* ranges, hipStream_t st);
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* blend_ctr, unsigned long long* visit_ctr,
-                  unsigned long long* eval_ctr, hipStream_t st);
+                  unsigned long long* slots, hipStream_t st);
+void launch_sum_slots(const unsigned long long* slots, unsigned long long* ctr, hipStream_t st);
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st);
 void launch_debug_log(const float* x, float* y, int64_t n, hipStream_t st);
 
