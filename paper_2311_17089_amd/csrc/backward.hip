@@ -43,6 +43,53 @@ __device__ __forceinline__ float wave_sum_to_63(float v) {
   return v;
 }
 
+// Sums over the wave of the nine partials of one instance, by a transposed
+// reduction: four DPP exchange stages inside each 16-lane row, each halving
+// the values a lane keeps (lane ^ 8 by row rotation, then the half-row mirror,
+// then lane ^ 2 and lane ^ 1), so that every lane ends with the row sum of one
+// of the nine values; two cross-row exchanges complete the wave sums.  Lane L
+// (L < 16) then holds the total of value kSlotQ(L) (15 = none).
+constexpr unsigned long long kSlotTable = 0xfff8f765ff43f210ull;
+__device__ __forceinline__ int slot_q(int lane) { return (int)((kSlotTable >> (4 * lane)) & 0xF); }
+
+#define MSGS_DPP(x, ctrl) \
+  __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false))
+
+__device__ __forceinline__ float wave_reduce9(const float (&v)[9], int lane) {
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+  float a[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const float hi = k < 4 ? v[5 + k] : 0.0f;
+    const float keep = b3 ? hi : v[k];
+    const float send = b3 ? v[k] : hi;
+    a[k] = keep + MSGS_DPP(send, 0x128);  // row_ror:8 (lane ^ 8 within the row)
+  }
+  float c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float hi = k < 2 ? a[3 + k] : 0.0f;
+    const float keep = b2 ? hi : a[k];
+    const float send = b2 ? a[k] : hi;
+    c[k] = keep + MSGS_DPP(send, 0x141);  // row_half_mirror (flips bit 2)
+  }
+  float d[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float hi = k == 0 ? c[2] : 0.0f;
+    const float keep = b1 ? hi : c[k];
+    const float send = b1 ? c[k] : hi;
+    d[k] = keep + MSGS_DPP(send, 0x4E);  // quad_perm [2,3,0,1]
+  }
+  const float keep = b0 ? d[1] : d[0];
+  const float send = b0 ? d[0] : d[1];
+  float e = keep + MSGS_DPP(send, 0xB1);  // quad_perm [1,0,3,2]
+  e += __shfl_xor(e, 16, 64);
+  e += __shfl_xor(e, 32, 64);
+  return e;
+}
+#undef MSGS_DPP
+
 __device__ __forceinline__ int xcd_tile_b(int b, int nblk) {
   (void)nblk;
   const int c = b >> 3;  // index of the workgroup within its XCD
@@ -170,11 +217,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
         }
       }
       if (__ballot(contrib)) {
+        float sm[kNP];
 #pragma unroll
-        for (int q = 0; q < kNP; ++q) {
-          const float sm = wave_sum_to_63(contrib ? g[q] : 0.0f);
-          if (lane == 63) red[q][wave][j] = sm;
-        }
+        for (int q = 0; q < kNP; ++q) sm[q] = contrib ? g[q] : 0.0f;
+        const float tot = wave_reduce9(sm, lane);
+        const int q = slot_q(lane & 15);
+        if (lane < 16 && q < kNP) red[q][wave][j] = tot;
       } else if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < kNP; ++q) red[q][wave][j] = 0.0f;
