@@ -70,11 +70,11 @@ def stage_bytes(st, n, sh_degree, passes_depth, passes_tile):
         "emit": nv * (4 + 4 + 8 + 4) + I * 8,
         "tile_sort": passes_tile * I * (4 + 16),
         "ranges": I * 4 + ntile * 8,
-        # zero fill of the per-instance partials (three float4 each)
-        "zero_bwd": I * 48,
+        # clear of the written-partial bit mask
+        "zero_bwd": (I + 31) // 32 * 4,
         # read the partials and tile counts, write/read the per-Gaussian sums,
         # read the parameters again, write every gradient plane
-        "chain_bwd": I * 36 + n * 8 + n * 72 + n * (53 + 12 * K) + n * (44 + 12 * K),
+        "chain_bwd": I // 8 + n * 8 + n * 72 + n * (53 + 12 * K) + n * (44 + 12 * K),
     }
 
 

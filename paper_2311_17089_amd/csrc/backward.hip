@@ -6,12 +6,16 @@
 //                the suffix colour B_j; the nine partial derivatives of every
 //                instance (d u, d conic, d sigma, d colour) are summed over the
 //                tile's 256 pixels by DPP wave reductions and a four-wave LDS
-//                sum, and written once to the instance's emission slot.  No
-//                atomics: the result is deterministic.
-//  k_seg_small / k_seg_big   per-Gaussian sum of its contiguous emission
-//                range of partials.  Threads walk the Gaussians in emission
-//                (depth) order so that a wave reads one contiguous span; a
-//                Gaussian with more than 64 tiles gets a workgroup.  Partials and
+//                sum, and written once to the instance's emission slot, with
+//                its bit set in a per-instance mask (most instances contribute
+//                to no pixel, so their partials are neither cleared nor read).
+//                The sums themselves use no atomics: the result is
+//                deterministic.
+//  k_seg_small / k_seg_big   per-Gaussian sum of the written partials of its
+//                contiguous emission range, in slot order.  Threads walk the
+//                Gaussians in emission (depth) order so that a wave reads one
+//                contiguous span; a Gaussian with more than 64 tiles gets a
+//                workgroup.  Partials and
 //                sums are stored as three float4 per instance / Gaussian.
 //  k_chain       chain rule per Gaussian from (u, conic, sigma, colour) to the
 //                scene parameters (means, linear scales, raw quaternion,
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
                                                       const uint32_t* emit_base, ViewParams v,
                                                       int ntile, const float* T_final,
                                                       const uint32_t* n_last, const float* dLdC,
-                                                      float* partial) {
+                                                      float* partial, uint32_t* wmask) {
   __shared__ float4 s0[kBB], s1[kBB], s2[kBB];
   __shared__ float red[kNP][kBlock / 64][kBB];
   __shared__ uint8_t lists[4][256];
@@ -246,16 +250,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
         P[0] = make_float4(sm[0], sm[1], sm[2], sm[3]);
         P[1] = make_float4(sm[4], sm[5], sm[6], sm[7]);
         P[2] = make_float4(sm[8], 0.0f, 0.0f, 0.0f);
+        atomicOr(&wmask[slot >> 5], 1u << (slot & 31u));
       }
     }
     __syncthreads();
     hi = lo;
   }
-}
-
-__global__ __launch_bounds__(kBlock) void k_fill_f4(float4* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) p[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 __device__ __forceinline__ void acc3(float* s, const float4* P) {
@@ -278,8 +278,8 @@ __device__ __forceinline__ void store3(float* gsum, int64_t k, const float* s) {
 __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int64_t n_vis,
                                                       const uint32_t* count,
                                                       const uint32_t* emit_base,
-                                                      const float* partial, float* gsum,
-                                                      uint32_t* big, uint32_t* nbig) {
+                                                      const float* partial, const uint32_t* wmask,
+                                                      float* gsum, uint32_t* big, uint32_t* nbig) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= n_vis) return;
   const uint32_t k = order[j];
@@ -291,26 +291,43 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
   float s[kNP];
 #pragma unroll
   for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
-  const float4* P = (const float4*)partial + (int64_t)emit_base[k] * 3;
-  for (uint32_t i = 0; i < c; ++i) acc3(s, P + 3 * i);
+  // only the slots whose partial was written (bit set) are read, in order
+  const uint32_t e0 = emit_base[k], e1 = e0 + c;
+  const float4* P = (const float4*)partial;
+  for (uint32_t w0 = e0 & ~31u; w0 < e1; w0 += 32u) {
+    uint32_t bits = wmask[w0 >> 5];
+    const uint32_t lo = e0 > w0 ? e0 - w0 : 0u;
+    const uint32_t hi = e1 - w0 >= 32u ? 32u : e1 - w0;
+    bits &= (hi == 32u ? ~0u : ((1u << hi) - 1u)) & (~0u << lo);
+    while (bits) {
+      const uint32_t b = (uint32_t)__ffs(bits) - 1u;
+      bits &= bits - 1u;
+      acc3(s, P + 3 * (int64_t)(w0 + b));
+    }
+  }
   store3(gsum, k, s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
                                                     const uint32_t* emit_base,
-                                                    const float* partial, float* gsum,
-                                                    const uint32_t* big, const uint32_t* nbig) {
+                                                    const float* partial, const uint32_t* wmask,
+                                                    float* gsum, const uint32_t* big,
+                                                    const uint32_t* nbig) {
   __shared__ float wred[kNP][kBlock / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t m = *nbig;
   for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
     const uint32_t k = big[i];
     const uint32_t c = count[k];
-    const float4* P = (const float4*)partial + (int64_t)emit_base[k] * 3;
+    const uint32_t e0 = emit_base[k];
+    const float4* P = (const float4*)partial;
     float s[kNP];
 #pragma unroll
     for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
-    for (uint32_t t = threadIdx.x; t < c; t += kBlock) acc3(s, P + 3 * t);
+    for (uint32_t t = threadIdx.x; t < c; t += kBlock) {
+      const uint32_t e = e0 + t;
+      if ((wmask[e >> 5] >> (e & 31u)) & 1u) acc3(s, P + 3 * (int64_t)e);
+    }
 #pragma unroll
     for (int q = 0; q < kNP; ++q) {
       const float r = wave_sum_to_63(s[q]);
@@ -471,10 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 void launch_backward_zero(const BwdArgs& a, hipStream_t st) {
-  if (a.n_inst > 0) {
-    const int64_t m = 3 * a.n_inst;
-    hipLaunchKernelGGL(k_fill_f4, dim3(grid_for(m)), dim3(kBlock), 0, st, (float4*)a.partial, m);
-  }
+  if (a.n_inst > 0) launch_fill_u32(a.wmask, (a.n_inst + 31) / 32, 0u, st);
 }
 
 void launch_backward_blend(const BwdArgs& a, hipStream_t st) {
@@ -482,7 +496,8 @@ void launch_backward_blend(const BwdArgs& a, hipStream_t st) {
   const int nblk = (ntile + 31) / 32 * 32;
   if (a.n_inst > 0) {
     hipLaunchKernelGGL(k_blend_bwd, dim3(nblk), dim3(kBlock), 0, st, a.ranges, a.tvals, a.rec,
-                       a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last, a.dL_drgb, a.partial);
+                       a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last, a.dL_drgb, a.partial,
+                       a.wmask);
   }
 }
 
@@ -491,9 +506,9 @@ void launch_backward_chain(const BwdArgs& a, hipStream_t st) {
   if (n == 0) return;
   if (a.n_vis > 0) {
     hipLaunchKernelGGL(k_seg_small, dim3(grid_for(a.n_vis)), dim3(kBlock), 0, st, a.order, a.n_vis,
-                       a.count, a.emit_base, a.partial, a.gsum, a.big, a.nbig);
+                       a.count, a.emit_base, a.partial, a.wmask, a.gsum, a.big, a.nbig);
     hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, a.partial,
-                       a.gsum, a.big, a.nbig);
+                       a.wmask, a.gsum, a.big, a.nbig);
   }
   const dim3 g(grid_for(n)), b(kBlock);
   switch (a.s.sh_degree) {

@@ -489,6 +489,7 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   a.g_sh = out->sh;
   Carve tmp;
   tmp.add(&a.partial, (size_t)48 * (size_t)f->n_inst);
+  tmp.add((void**)&a.wmask, (size_t)4 * (size_t)((f->n_inst + 31) / 32));
   tmp.add(&a.gsum, (size_t)48 * (size_t)n);
   tmp.add(&a.big, (size_t)4 * (size_t)n);
   tmp.add(&a.nbig, 4);
