@@ -179,47 +179,45 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
     for (int i = 0; i < nl; ++i) {
       const int j = lists[wave][i];
       const uint32_t pos = hi - 1 - (uint32_t)j - rg.x;  // position in the tile list
+      // branch-free: every lane evaluates the entry (a wave runs the code
+      // whenever one lane needs it); lanes that do not contribute keep T and B
+      // and contribute zeros to the sums
+      const float4 a = s0[j];
+      const float4 b = s1[j];
+      const float4 c = s2[j];
+      const float dx = pcx - a.x;
+      const float dy = pcy - a.y;
+      const float qxx = dx * dx, qyy = dy * dy, qxy = dx * dy;
+      const float e = -0.5f * (a.z * qxx + b.x * qyy);
+      const float power = e - a.w * qxy;
+      const float ex = exp_c(power);
+      const float ar = b.y * ex;
+      const bool contrib = pos < last && !(power > 0.0f || power < b.z) && !(ar < kAlphaMin);
+      const float c0 = b.w, c1 = c.x, c2 = c.y;
+      const float al = fminf(kAlphaMax, ar);
+      // the replay is not part of the bit-exact contract: the hardware
+      // reciprocal (1 ulp) replaces the correctly rounded division
+      const float om = __builtin_amdgcn_rcpf(1.0f - al);
+      const float Tb = T * om;
+      const float w = al * Tb;
       float g[kNP];
-      bool contrib = false;
-      if (pos < last) {
-        const float4 a = s0[j];
-        const float4 b = s1[j];
-        const float dx = pcx - a.x;
-        const float dy = pcy - a.y;
-        const float qxx = dx * dx, qyy = dy * dy, qxy = dx * dy;
-        const float e = -0.5f * (a.z * qxx + b.x * qyy);
-        const float power = e - a.w * qxy;
-        if (!(power > 0.0f || power < b.z)) {
-          const float ex = exp_c(power);
-          const float ar = b.y * ex;
-          if (!(ar < kAlphaMin)) {
-            contrib = true;
-            const float4 c = s2[j];
-            const float c0 = b.w, c1 = c.x, c2 = c.y;
-            const float al = fminf(kAlphaMax, ar);
-            const float om = 1.0f / (1.0f - al);
-            const float Tb = T * om;
-            const float w = al * Tb;
-            g[6] = d0 * w;
-            g[7] = d1 * w;
-            g[8] = d2 * w;
-            const float dal = d0 * (c0 * Tb - B0 * om) + d1 * (c1 * Tb - B1 * om) +
-                              d2 * (c2 * Tb - B2 * om);
-            B0 += c0 * w;
-            B1 += c1 * w;
-            B2 += c2 * w;
-            T = Tb;
-            const float dar = ar > kAlphaMax ? 0.0f : dal;
-            g[5] = dar * ex;
-            const float dp = dar * ar;
-            g[2] = dp * (-0.5f * qxx);
-            g[3] = dp * (-qxy);
-            g[4] = dp * (-0.5f * qyy);
-            g[0] = dp * (a.z * dx + a.w * dy);
-            g[1] = dp * (b.x * dy + a.w * dx);
-          }
-        }
-      }
+      g[6] = d0 * w;
+      g[7] = d1 * w;
+      g[8] = d2 * w;
+      const float dal = d0 * (c0 * Tb - B0 * om) + d1 * (c1 * Tb - B1 * om) +
+                        d2 * (c2 * Tb - B2 * om);
+      B0 = contrib ? B0 + c0 * w : B0;
+      B1 = contrib ? B1 + c1 * w : B1;
+      B2 = contrib ? B2 + c2 * w : B2;
+      T = contrib ? Tb : T;
+      const float dar = ar > kAlphaMax ? 0.0f : dal;
+      g[5] = dar * ex;
+      const float dp = dar * ar;
+      g[2] = dp * (-0.5f * qxx);
+      g[3] = dp * (-qxy);
+      g[4] = dp * (-0.5f * qyy);
+      g[0] = dp * (a.z * dx + a.w * dy);
+      g[1] = dp * (b.x * dy + a.w * dx);
       if (__ballot(contrib)) {
         float sm[kNP];
 #pragma unroll
