@@ -170,6 +170,11 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       s1[threadIdx.x] = n1;
       s2[threadIdx.x] = n2;
       qm = quad_mask(n0.x, n0.y, n2.z, n2.w, x0, y0);
+      // a quadrant skips the instances at or past its last contributor
+      const uint32_t pos_t = hi - 1 - threadIdx.x - rg.x;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w)
+        if (pos_t >= smax[w]) qm &= ~(1u << w);
     }
     build_wave_lists(qm, have, lists, len, wcnt);
     const uint32_t nlo = lo - rg.x > (uint32_t)kBB ? lo - kBB : rg.x;
