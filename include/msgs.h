@@ -139,14 +139,18 @@ typedef struct {
 
 /* Gradient outputs, caller-owned device planar buffers with the scene's
  * layout: dL/d means, dL/d scales (linear), dL/d quats (raw, un-normalised),
- * dL/d opacity (sigma), dL/d sh.  Written, not accumulated; Gaussians that do
- * not contribute get 0. */
+ * dL/d opacity (sigma), dL/d sh.  accumulate = 0: written; Gaussians that do
+ * not contribute get 0.  accumulate = 1: this frame's gradient is added to
+ * the planes and Gaussians that do not contribute are left untouched (a
+ * multi-view step zeroes the planes once and accumulates every view; calls
+ * that accumulate into the same planes must be ordered, e.g. on one stream). */
 typedef struct {
   float* means;
   float* scales;
   float* quats;
   float* opacity;
   float* sh;
+  int accumulate;
 } msgs_grads;
 
 int msgs_version(void);

@@ -348,8 +348,18 @@ __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
 }
 
 // Chain rule per Gaussian (SH degree D as a template parameter so that the
-// coefficient loads are issued together).
-template <int D>
+// coefficient loads are issued together).  ACC: add into the gradient planes
+// instead of writing them; Gaussians that do not contribute are then not
+// touched at all.
+template <bool ACC>
+__device__ __forceinline__ void put(float* p, int64_t i, float x) {
+  if (ACC)
+    p[i] += x;
+  else
+    p[i] = x;
+}
+
+template <int D, bool ACC>
 __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, const uint32_t* count,
                                                   const float* gsum, float* g_means,
                                                   float* g_scales, float* g_quats,
@@ -361,6 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
   Geo g;
   bool live = count[k] > 0 && project_geo(s, v, k, g);
   if (!live) {
+    if (ACC) return;
     for (int i = 0; i < 3; ++i) g_means[i * n + k] = 0.0f;
     for (int i = 0; i < 3; ++i) g_scales[i * n + k] = 0.0f;
     for (int i = 0; i < 4; ++i) g_quats[i * n + k] = 0.0f;
@@ -378,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
     G[8] = c.x;
   }
   const float gux = G[0], guy = G[1], gA11 = G[2], gA12 = G[3], gA22 = G[4];
-  g_opacity[k] = G[5];
+  put<ACC>(g_opacity, k, G[5]);
   // ---- colour -> SH coefficients and view direction
   const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
   float dv0 = mu0 - v.C[0], dv1 = mu1 - v.C[1], dv2 = mu2 - v.C[2];
@@ -399,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
     const float gc = acc < 0.0f ? 0.0f : G[6 + c];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      g_sh[(int64_t)(j * 3 + c) * n + k] = Y[j] * gc;
+      put<ACC>(g_sh, (int64_t)(j * 3 + c) * n + k, Y[j] * gc);
       gdx += gc * f[j * 3 + c] * Yx[j];
       gdy += gc * f[j * 3 + c] * Yy[j];
       gdz += gc * f[j * 3 + c] * Yz[j];
@@ -455,9 +466,9 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
   gm0 += R[0] * gp0 + R[3] * gp1 + R[6] * gp2;
   gm1 += R[1] * gp0 + R[4] * gp1 + R[7] * gp2;
   gm2 += R[2] * gp0 + R[5] * gp1 + R[8] * gp2;
-  g_means[k] = gm0;
-  g_means[n + k] = gm1;
-  g_means[2 * n + k] = gm2;
+  put<ACC>(g_means, k, gm0);
+  put<ACC>(g_means, n + k, gm1);
+  put<ACC>(g_means, 2 * n + k, gm2);
   // ---- Sigma = M M^T, M = Q diag(s)
   float M[3][3];
   for (int i = 0; i < 3; ++i)
@@ -467,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
     for (int j = 0; j < 3; ++j) gM[i][j] = Gs[i][0] * M[0][j] + Gs[i][1] * M[1][j] + Gs[i][2] * M[2][j];
   float gQ[9];
   for (int j = 0; j < 3; ++j) {
-    g_scales[j * n + k] = gM[0][j] * g.Q[j] + gM[1][j] * g.Q[3 + j] + gM[2][j] * g.Q[6 + j];
+    put<ACC>(g_scales, j * n + k, gM[0][j] * g.Q[j] + gM[1][j] * g.Q[3 + j] + gM[2][j] * g.Q[6 + j]);
     for (int i = 0; i < 3; ++i) gQ[i * 3 + j] = gM[i][j] * g.sc[j];
   }
   // ---- Q(q_hat) -> q_hat -> raw q
@@ -482,10 +493,10 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
                    4.0f * qz * gQ[4] + 2.0f * qy * gQ[5] + 2.0f * qx * gQ[6] + 2.0f * qy * gQ[7];
   const float dq = w * gw + qx * gx + qy * gy + qz * gz;
   const float il = 1.0f / g.qlen;
-  g_quats[k] = (gw - w * dq) * il;
-  g_quats[n + k] = (gx - qx * dq) * il;
-  g_quats[2 * n + k] = (gy - qy * dq) * il;
-  g_quats[3 * n + k] = (gz - qz * dq) * il;
+  put<ACC>(g_quats, k, (gw - w * dq) * il);
+  put<ACC>(g_quats, n + k, (gx - qx * dq) * il);
+  put<ACC>(g_quats, 2 * n + k, (gy - qy * dq) * il);
+  put<ACC>(g_quats, 3 * n + k, (gz - qz * dq) * il);
 }
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -504,6 +515,16 @@ void launch_backward_blend(const BwdArgs& a, hipStream_t st) {
   }
 }
 
+template <int D>
+static void launch_chain_d(const BwdArgs& a, dim3 g, dim3 b, hipStream_t st) {
+  if (a.accumulate)
+    hipLaunchKernelGGL((k_chain<D, true>), g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means,
+                       a.g_scales, a.g_quats, a.g_opacity, a.g_sh);
+  else
+    hipLaunchKernelGGL((k_chain<D, false>), g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means,
+                       a.g_scales, a.g_quats, a.g_opacity, a.g_sh);
+}
+
 void launch_backward_chain(const BwdArgs& a, hipStream_t st) {
   const int64_t n = a.s.n;
   if (n == 0) return;
@@ -515,10 +536,10 @@ void launch_backward_chain(const BwdArgs& a, hipStream_t st) {
   }
   const dim3 g(grid_for(n)), b(kBlock);
   switch (a.s.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_chain<0>, g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh); break;
-    case 1: hipLaunchKernelGGL(k_chain<1>, g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh); break;
-    case 2: hipLaunchKernelGGL(k_chain<2>, g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh); break;
-    default: hipLaunchKernelGGL(k_chain<3>, g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh); break;
+    case 0: launch_chain_d<0>(a, g, b, st); break;
+    case 1: launch_chain_d<1>(a, g, b, st); break;
+    case 2: launch_chain_d<2>(a, g, b, st); break;
+    default: launch_chain_d<3>(a, g, b, st); break;
   }
 }
 

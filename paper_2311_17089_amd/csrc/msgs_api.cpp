@@ -487,6 +487,7 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   a.g_quats = out->quats;
   a.g_opacity = out->opacity;
   a.g_sh = out->sh;
+  a.accumulate = out->accumulate ? 1 : 0;
   Carve tmp;
   tmp.add(&a.partial, (size_t)48 * (size_t)f->n_inst);
   tmp.add((void**)&a.wmask, (size_t)4 * (size_t)((f->n_inst + 31) / 32));

@@ -67,6 +67,7 @@ struct BwdArgs {
   float* g_quats;
   float* g_opacity;
   float* g_sh;
+  int accumulate;           // add into the gradient planes instead of writing them
 };
 void launch_backward_zero(const BwdArgs& a, hipStream_t st);
 void launch_backward_blend(const BwdArgs& a, hipStream_t st);

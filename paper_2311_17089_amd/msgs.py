@@ -54,7 +54,7 @@ class Stats(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
-                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("accumulate", C.c_int)]
 
 
 class Completion(C.Structure):
@@ -284,13 +284,26 @@ def render(ctx: Context, scene: DeviceScene, cam, downscale=1, selective=True,
     return out
 
 
-def render_backward(ctx: Context, frame: Frame, dL_drgb: torch.Tensor, stream=None) -> dict:
+def render_backward(ctx: Context, frame: Frame, dL_drgb: torch.Tensor, stream=None,
+                    grads: Optional[dict] = None, accumulate: bool = False) -> dict:
     """Adjoint of `render` for the frame's decisions; returns gradient tensors
-    w.r.t. means, scales (linear), quats (raw), opacity and sh."""
+    w.r.t. means, scales (linear), quats (raw), opacity and sh.  With `grads`
+    (tensors shaped like the scene's) they receive the result; with
+    accumulate=True it is added to them."""
     sc = frame.scene
     assert dL_drgb.is_contiguous() and dL_drgb.dtype == torch.float32
-    g = {k: torch.empty_like(sc.t[k]) for k in ("means", "scales", "quats", "opacity", "sh")}
-    gs = Grads(*[g[k].data_ptr() for k in ("means", "scales", "quats", "opacity", "sh")])
+    names = ("means", "scales", "quats", "opacity", "sh")
+    if grads is None:
+        if accumulate:
+            raise ValueError("accumulate needs caller-owned grads")
+        g = {k: torch.empty_like(sc.t[k]) for k in names}
+    else:
+        g = grads
+        for k in names:
+            t = g[k]
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+            assert t.shape == sc.t[k].shape, k
+    gs = Grads(*[g[k].data_ptr() for k in names], 1 if accumulate else 0)
     check(lib().msgs_render_backward(ctx.h, frame.h, C.c_void_p(dL_drgb.data_ptr()), C.byref(gs),
                                      C.c_void_p(_stream(stream))))
     return g
