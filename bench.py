@@ -161,6 +161,53 @@ def serving_replay(M, G, n_req=512, rate_hz=200.0, inflight=4, selective=True):
             "p50_ms_by_downscale": {str(k): float(np.percentile(v, 50)) for k, v in sorted(per_ds.items())}}
 
 
+def training_step(M, G, steps=5, warmup=2):
+    """Multi-view training step on the 6M-Gaussian, 5-level scene: 8 views
+    (seeded poses on a sphere of radius 2-12), one at each downscale 1, 2, ...,
+    128 of 1920x1080, each rendered with the range update on and its backward
+    accumulated into one set of gradient planes, all on one stream.  dL/dRGB is
+    a fixed seeded tensor per view.  Returns step time and blends per second."""
+    import numpy as np
+    import torch
+    ctx = M.Context(0)
+    sc = G.large_scene(6_000_000, 5, 5)
+    dsc = M.DeviceScene(ctx, sc)
+    M.calibrate(ctx, dsc, G.calibration_cameras(1005, 1920, 1080, 2250.0))
+    poses = G.sphere_poses(8, 5, 2.0, 12.0)
+    views = [(G.lookat_camera(poses[i], 1920, 1080, 2250.0), 2 ** i) for i in range(8)]
+    dls = [torch.randn((1080 // d, 1920 // d, 3), generator=torch.Generator().manual_seed(900 + i))
+           .cuda() * 1e-6 for i, (_, d) in enumerate(views)]
+    names = ("means", "scales", "quats", "opacity", "sh")
+    grads = {k: torch.zeros_like(dsc.t[k]) for k in names}
+    blends = [0]
+
+    def step(count=False):
+        for g in grads.values():
+            g.zero_()
+        for (cam, d), dl in zip(views, dls):
+            _, fr = M.render(ctx, dsc, cam, downscale=d, update_range=True, keep_frame=True)
+            M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
+            if count:
+                blends[0] += fr.stats()["n_blends"]
+            fr.release()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    step(count=True)
+    torch.cuda.synchronize()
+    dsc.close()
+    return {"workload": "6M Gaussians over 5 levels (SH degree 3), 8 views at 1920x1080 / "
+                        "{1,2,...,128}, range update on, gradients accumulated",
+            "ms_per_step": dt * 1e3, "blends_per_step": blends[0],
+            "blends_per_s": blends[0] / dt, "steps": steps, "graph": False}
+
+
 def traffic_for(kernel, launch):
     """HBM traffic of the dominant kernel from the committed rocprofv3 counter
     summary, if it was taken from the current kernel source."""
@@ -188,6 +235,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-training", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one serial step and a 1 GiB elementwise copy, for HBM counter runs")
@@ -400,6 +448,9 @@ def main():
               flush=True)
         out["serving"] = {"selective": serving_replay(M, G, selective=True),
                           "single_scale": serving_replay(M, G, selective=False)}
+    if not args.no_training:
+        print("bench: training step (6M Gaussians, 8 views)", file=sys.stderr, flush=True)
+        out["training_step"] = training_step(M, G)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
