@@ -196,6 +196,38 @@ int msgs_render(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
 int msgs_render_backward(msgs_context* ctx, const msgs_frame* frame, const float* dL_drgb,
                          const msgs_grads* out, void* stream);
 
+/* Planar Gaussians produced by the library (caller-owned device arrays with
+ * room for `cap` Gaussians, same layout as msgs_scene_desc with n = cap). */
+typedef struct {
+  float* means;    /* [3][cap] */
+  float* scales;   /* [3][cap] linear */
+  float* quats;    /* [4][cap] unit (w, x, y, z) */
+  float* opacity;  /* [cap] */
+  float* sh;       /* [3 (D+1)^2][cap] */
+  int64_t cap;
+} msgs_gaussians;
+
+/* Coarse-level aggregation (Alg. 1 for one target level; supplementary
+ * "Details of Gaussian Aggregation"):
+ *   every Gaussian of a level below `level` is projected with every camera of
+ *   `cams` at downscale 4^level; its pixel coverage counts for a camera that
+ *   draws it (in front, non-empty level set, at least one tile); Gaussians whose
+ *   smallest such coverage is below s_thresh (S_T, 2 px) are binned by their
+ *   normalised position (x / extent inside the cube of half side `extent`,
+ *   (2 - extent / m) x / m outside, m the max-norm) on a grid of `grid` voxels
+ *   per axis over [-2, 2]^3 (the paper uses grid = floor(400 / (level + 1)));
+ *   each occupied voxel yields one Gaussian: the mean position, unit rotation,
+ *   linear scale, opacity and SH of its members, the scale multiplied by
+ *   s_thresh / (mean coverage of the members).
+ * The new Gaussians are written in ascending voxel order to `out`; *n_out
+ * receives their number.  Synchronous.  Errors: MSGS_E_INVALID (level outside
+ * [1, n_levels - 1], grid outside [1, 255], non-positive extent or threshold,
+ * no camera), MSGS_E_CAPACITY (more than out->cap Gaussians: *n_out holds the
+ * number needed and nothing is written). */
+int msgs_aggregate_level(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cams,
+                         int ncams, int level, float s_thresh, float extent, int grid,
+                         const msgs_gaussians* out, int64_t* n_out, void* stream);
+
 /* Release a frame (its device memory is returned on the frame's stream). */
 int msgs_frame_release(msgs_frame* f);
 /* Statistics of a frame (synchronises the frame's stream). */

@@ -378,6 +378,88 @@ int msgs_scene_get_ranges(const msgs_scene* s, float* smax, float* smin) {
   return MSGS_OK;
 }
 
+int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams, int ncams,
+                         int level, float s_thresh, float extent, int grid,
+                         const msgs_gaussians* out, int64_t* n_out, void* stream) {
+  if (!c || !s || !cams || !out || !n_out) return fail(MSGS_E_INVALID, "null argument");
+  if (s->ctx != c) return fail(MSGS_E_INVALID, "scene belongs to another context");
+  if (ncams < 1) return fail(MSGS_E_INVALID, "at least one camera is needed");
+  if (level < 1 || level >= s->view.n_levels)
+    return fail(MSGS_E_INVALID, "target level must be in [1, n_levels - 1]");
+  if (level > 12) return fail(MSGS_E_INVALID, "target level too large");
+  if (grid < 1 || grid > 255) return fail(MSGS_E_INVALID, "grid must be in [1, 255]");
+  if (!(extent > 0.0f) || !(s_thresh > 0.0f))
+    return fail(MSGS_E_INVALID, "extent and threshold must be positive");
+  if (out->cap < 0 || (out->cap > 0 && (!out->means || !out->scales || !out->quats ||
+                                        !out->opacity || !out->sh)))
+    return fail(MSGS_E_INVALID, "null output array");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = s->view.n;
+  *n_out = 0;
+  if (n == 0) return MSGS_OK;
+  std::vector<ViewParams> hv((size_t)ncams);
+  msgs_render_opts o;
+  msgs_default_opts(&o);
+  o.downscale = 1 << (2 * level);
+  o.selective = 0;
+  for (int i = 0; i < ncams; ++i) {
+    int rc = make_view(&cams[i], &o, s->view.n_levels, &hv[(size_t)i]);
+    if (rc != MSGS_OK) return rc;
+  }
+  ViewParams* dv = nullptr;
+  uint32_t *keys = nullptr, *vals = nullptr, *keys2 = nullptr, *vals2 = nullptr;
+  uint32_t *heads = nullptr, *segidx = nullptr, *starts = nullptr;
+  float* smin = nullptr;
+  unsigned long long* ctr = nullptr;
+  void *stmp = nullptr, *ctmp = nullptr;
+  Carve tmp;
+  tmp.add((void**)&dv, sizeof(ViewParams) * (size_t)ncams);
+  tmp.add((void**)&keys, (size_t)n * 4);
+  tmp.add((void**)&vals, (size_t)n * 4);
+  tmp.add((void**)&keys2, (size_t)n * 4);
+  tmp.add((void**)&vals2, (size_t)n * 4);
+  tmp.add((void**)&heads, (size_t)n * 4);
+  tmp.add((void**)&segidx, (size_t)n * 4);
+  tmp.add((void**)&starts, (size_t)(n + 1) * 4);
+  tmp.add((void**)&smin, (size_t)n * 4);
+  tmp.add((void**)&ctr, 16);
+  tmp.add(&ctmp, scan_tmp_bytes(n));
+  tmp.add(&stmp, radix_tmp_bytes(n, radix_passes(0, 24)));
+  int rc = tmp.alloc(c, st);
+  if (rc != MSGS_OK) return rc;
+  e = hipMemcpyAsync(dv, hv.data(), sizeof(ViewParams) * (size_t)ncams, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    launch_agg_cover(s->view, dv, ncams, level, s_thresh, extent, grid, keys, vals, smin, st);
+    // stable sort by voxel (the 24-bit key): ends in the second buffers after 3 passes
+    const int odd = radix_sort_pairs(keys, vals, keys2, vals2, nullptr, n, 0, 24, stmp, st);
+    const uint32_t* sk = odd ? keys2 : keys;
+    const uint32_t* sv = odd ? vals2 : vals;
+    launch_agg_heads(sk, n, heads, st);
+    scan_excl_u32(heads, nullptr, segidx, nullptr, n, ctr, ctmp, st);
+    launch_agg_starts(sk, heads, segidx, n, starts, st);
+    unsigned long long nseg = 0;
+    e = hipMemcpyAsync(&nseg, ctr, sizeof nseg, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) {
+      *n_out = (int64_t)nseg;
+      if ((int64_t)nseg > out->cap) {
+        rc = fail(MSGS_E_CAPACITY, "aggregation output needs " + std::to_string(nseg) +
+                                       " Gaussians, capacity " + std::to_string(out->cap));
+      } else {
+        launch_agg_reduce(s->view, sv, starts, (int64_t)nseg, smin, s_thresh, out->means,
+                          out->scales, out->quats, out->opacity, out->sh, out->cap, st);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+      }
+    }
+  }
+  if (e != hipSuccess) rc = hip_fail(e, "aggregation");
+  c->cache.free(c, tmp.base, st);
+  return rc;
+}
+
 int msgs_render(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
                 const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
                 void* stream) {

@@ -73,4 +73,17 @@ void launch_backward_zero(const BwdArgs& a, hipStream_t st);
 void launch_backward_blend(const BwdArgs& a, hipStream_t st);
 void launch_backward_chain(const BwdArgs& a, hipStream_t st);
 
+// aggregation (Alg. 1): voxel key of a Gaussian that is not chosen
+constexpr uint32_t kAggNone = 0xFFFFFFu;
+void launch_agg_cover(const SceneView& s, const ViewParams* views, int ncams, int level,
+                      float s_thresh, float B, int R, uint32_t* keys, uint32_t* vals, float* smin,
+                      hipStream_t st);
+void launch_agg_heads(const uint32_t* keys, int64_t n, uint32_t* heads, hipStream_t st);
+void launch_agg_starts(const uint32_t* keys, const uint32_t* heads, const uint32_t* segidx,
+                       int64_t n, uint32_t* starts, hipStream_t st);
+void launch_agg_reduce(const SceneView& s, const uint32_t* vals, const uint32_t* starts,
+                       int64_t nseg, const float* smin, float s_thresh, float* o_means,
+                       float* o_scales, float* o_quats, float* o_opacity, float* o_sh, int64_t cap,
+                       hipStream_t st);
+
 }  // namespace msgs

@@ -57,6 +57,11 @@ class Grads(C.Structure):
                 ("opacity", C.c_void_p), ("sh", C.c_void_p), ("accumulate", C.c_int)]
 
 
+class Gaussians(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("cap", C.c_int64)]
+
+
 class Completion(C.Structure):
     _fields_ = [("req_id", C.c_uint64), ("status", C.c_int), ("t_submit_us", C.c_double),
                 ("t_admit_us", C.c_double), ("t_start_us", C.c_double), ("t_done_us", C.c_double),
@@ -94,6 +99,8 @@ EXPORTS = {
     "msgs_server_poll": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int], C.c_int),
     "msgs_server_pending": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "msgs_server_destroy": ([C.c_void_p], C.c_int),
+    "msgs_aggregate_level": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_float,
+                              C.c_float, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
 }
 
 
@@ -422,3 +429,67 @@ class Server:
         if self.h:
             check(lib().msgs_server_destroy(self.h))
             self.h = None
+
+
+def camera_extent(cams) -> float:
+    """Half side of the origin-centred axis-aligned cube holding every camera
+    centre (-R^T t), as fp32: the default normalisation extent of aggregation."""
+    b = 0.0
+    for cam in cams:
+        R = np.asarray(cam.R, np.float64).reshape(3, 3)
+        c = -R.T @ np.asarray(cam.t, np.float64)
+        b = max(b, float(np.abs(c).max()))
+    return float(np.float32(b))
+
+
+def aggregate_level(ctx: Context, scene: DeviceScene, cams, level: int, s_thresh: float = 2.0,
+                    extent: Optional[float] = None, grid: Optional[int] = None,
+                    stream=None) -> dict:
+    """New Gaussians of `level` aggregated from the small Gaussians below it
+    (see msgs_aggregate_level); returns device tensors in voxel order."""
+    extent = camera_extent(cams) if extent is None else float(extent)
+    grid = 400 // (level + 1) if grid is None else int(grid)
+    dev = scene.t["means"].device
+    cap = max(1, int((scene.t["level"] < level).sum().item()))
+    K3 = 3 * (scene.sh_degree + 1) ** 2
+    out = {"means": torch.empty((3, cap), device=dev), "scales": torch.empty((3, cap), device=dev),
+           "quats": torch.empty((4, cap), device=dev), "opacity": torch.empty(cap, device=dev),
+           "sh": torch.empty((K3, cap), device=dev)}
+    g = Gaussians(*[out[k].data_ptr() for k in ("means", "scales", "quats", "opacity", "sh")], cap)
+    arr = (CameraC * len(cams))(*[camera_c(c) for c in cams])
+    n_out = C.c_int64()
+    check(lib().msgs_aggregate_level(ctx.h, scene.h, arr, len(cams), int(level), float(s_thresh),
+                                     float(extent), grid, C.byref(g), C.byref(n_out),
+                                     C.c_void_p(_stream(stream))))
+    m = n_out.value
+    return {k: v[..., :m].contiguous() for k, v in out.items()}
+
+
+def build_levels(ctx: Context, scene0, cams, n_levels: int, s_thresh: float = 2.0):
+    """Alg. 1 over every coarse level: starting from the level-0 Gaussians of
+    `scene0` (numpy scenegen.Scene), aggregate for l = 1 .. n_levels - 1 and
+    append each new level (uncalibrated range).  Returns the numpy scene and
+    the number of Gaussians added per level."""
+    import dataclasses
+    from .scenegen import Scene
+    scene = dataclasses.replace(scene0, n_levels=n_levels)
+    extent = camera_extent(cams)
+    added = []
+    for l in range(1, n_levels):
+        dsc = DeviceScene(ctx, scene)
+        part = aggregate_level(ctx, dsc, cams, l, s_thresh, extent)
+        torch.cuda.synchronize()
+        dsc.close()
+        m = part["opacity"].numel()
+        added.append(m)
+        host = {k: v.cpu().numpy() for k, v in part.items()}
+        scene = Scene(n=scene.n + m, sh_degree=scene.sh_degree, n_levels=n_levels,
+                      means=np.ascontiguousarray(np.concatenate([scene.means, host["means"]], 1)),
+                      scales=np.ascontiguousarray(np.concatenate([scene.scales, host["scales"]], 1)),
+                      quats=np.ascontiguousarray(np.concatenate([scene.quats, host["quats"]], 1)),
+                      opacity=np.ascontiguousarray(np.concatenate([scene.opacity, host["opacity"]])),
+                      sh=np.ascontiguousarray(np.concatenate([scene.sh, host["sh"]], 1)),
+                      level=np.concatenate([scene.level, np.full(m, l, np.uint8)]),
+                      s_max=np.concatenate([scene.s_max, np.zeros(m, np.float32)]),
+                      s_min=np.concatenate([scene.s_min, np.full(m, np.inf, np.float32)]))
+    return scene, added
