@@ -113,6 +113,8 @@ typedef struct {
   float near_z;
   float bg[3];
   int profile;
+  int no_prefilter;  /* 1: skip the conservative pre-splat bound (results are
+                        identical either way; for checks and measurement) */
 } msgs_render_opts;
 
 typedef struct {
@@ -135,6 +137,8 @@ typedef struct {
    * [9] whole forward (first to last stage, excluding the host wait)
    * [10] backward: zeroing of the per-instance partials  [11] whole backward */
   float stage_us[12];
+  int64_t n_prefiltered; /* Gaussians the pre-splat bound proved unselected
+                            (no rotation load, no EWA projection) */
 } msgs_stats;
 
 /* Gradient outputs, caller-owned device planar buffers with the scene's

@@ -22,6 +22,38 @@
 
 namespace msgs {
 
+// Pre-splat bound (the paper's stated limitation is that every Gaussian is
+// splatted whatever the resolution): from the view-space centre, the scale
+// extremes and the opacity, a bracket [lo, hi] of the pixel coverage.  With
+// s_min <= s_mid <= s_max the scales and J the perspective Jacobian (fx, fy),
+// the eigenvalues of J J^T are (f/z)^2 and (f/z)^2 (1 + (x/z)^2 + (y/z)^2), so
+//   lambda_min(V) >= s_min^2 (min f / z)^2,
+//   lambda_min(V) <= s_mid^2 (max f / z)^2 (1 + (x/z)^2 + (y/z)^2),
+// and S^2 = 8 lnq det V / max(V11, V22) lies in [8 lnq lambda_min, 16 lnq
+// lambda_min].  A relative margin of 1e-3 covers the fp32 rounding of both
+// sides.  Returns true only when the selection test is certain to fail; the
+// exact path then never runs (no rotation load, no EWA), and the selection
+// mask is the same bit for bit.
+__device__ __forceinline__ bool prefilter_unselected(const SceneView& s, const ViewParams& v,
+                                                     int64_t k, int l, float lnq) {
+  const int64_t n = s.n;
+  const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
+  const float px = ((v.R[0] * mu0 + v.R[1] * mu1) + v.R[2] * mu2) + v.t[0];
+  const float py = ((v.R[3] * mu0 + v.R[4] * mu1) + v.R[5] * mu2) + v.t[1];
+  const float pz = ((v.R[6] * mu0 + v.R[7] * mu1) + v.R[8] * mu2) + v.t[2];
+  if (!(pz > 1.001f * v.near_z)) return false;  // depth near the plane: exact path
+  const float s0 = s.scales[k], s1 = s.scales[n + k], s2 = s.scales[2 * n + k];
+  const float smn = fminf(fminf(s0, s1), s2);
+  const float smd = fmaxf(fminf(s0, s1), fminf(fmaxf(s0, s1), s2));
+  const float xr = px / pz, yr = py / pz;
+  const float flo = fminf(v.fx, v.fy) / pz, fhi = fmaxf(v.fx, v.fy) / pz;
+  const float lo = sqrtf(8.0f * lnq) * flo * smn * 0.999f;
+  const float hi = sqrtf(16.0f * lnq * (1.0f + (xr * xr + yr * yr))) * fhi * smd * 1.001f;
+  const bool g1_fails = l > 0 && lo > 1.5f * s.s_max[k];
+  const bool g2_fails = l < s.n_levels - 1 && hi < 0.5f * s.s_min[k] && hi < 2.0f;
+  return g1_fails || g2_fails;
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, uint8_t* sel_out,
                                                     uint32_t* count, uint32_t* depthkey,
@@ -31,20 +63,23 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, u
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   uint32_t ntiles = 0;
   int selected = 0;
+  int culled = 0;
   if (k < n) {
     Geo g;
-    bool front = project_geo(s, v, k, g);
-    float sig = s.opacity[k];
-    float y255 = 255.0f * sig;
-    bool vis = y255 > 1.0f;
-    float lnq = 0.0f;
+    const float sig = s.opacity[k];
+    const float y255 = 255.0f * sig;
+    const bool vis = y255 > 1.0f;
+    const float lnq = vis ? log_c(y255) : 0.0f;
+    const int l = s.level[k];
+    const bool skip = v.prefilter && v.selective && vis && l != v.update_level &&
+                      prefilter_unselected(s, v, k, l, lnq);
+    culled = skip ? 1 : 0;
+    const bool front = !skip && project_geo(s, v, k, g);
     float S = 0.0f;
     bool sel = false;
     if (front) {
-      lnq = vis ? log_c(y255) : 0.0f;
       S = coverage(g.V11, g.V12, g.V22, vis, lnq);
       sel = true;
-      const int l = s.level[k];
       if (v.selective) {
         bool g1 = (l == 0) || (S <= 1.5f * s.s_max[k]);
         bool g2 = (l == s.n_levels - 1) || (S >= 0.5f * s.s_min[k]) || (S >= 2.0f);
@@ -111,9 +146,12 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, u
   }
   int c = __syncthreads_count(ntiles > 0);
   int cs = __syncthreads_count(selected);
+  int cc = __syncthreads_count(culled);
   if (threadIdx.x == 0) {
     blk_vis[blockIdx.x] = (uint32_t)c;
-    if (cs) atomicAdd(&slots[(blockIdx.x % kCtrSlots) * 4 + 0], (unsigned long long)cs);
+    unsigned long long* sl = slots + (blockIdx.x % kCtrSlots) * kSlotW;
+    if (cs) atomicAdd(sl + 0, (unsigned long long)cs);
+    if (cc) atomicAdd(sl + 4, (unsigned long long)cc);
   }
 }
 
@@ -365,30 +403,30 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
   }
   const unsigned long long e64 =
       (unsigned long long)wev * (unsigned long long)__popcll(__ballot(inside));
-  unsigned long long* sl = slots + (blockIdx.x % kCtrSlots) * 4;
+  unsigned long long* sl = slots + (blockIdx.x % kCtrSlots) * kSlotW;
   if (lane == 0 && c64) atomicAdd(sl + 1, c64);
   if (lane == 0 && v64) atomicAdd(sl + 2, v64);
   if (lane == 0 && e64) atomicAdd(sl + 3, e64);
 }
 
 // Totals of the counter slots: ctr[0] selected, ctr[1] blends, ctr[4] visits,
-// ctr[5] evaluations (fixed summation order).
+// ctr[5] evaluations, ctr[6] prefiltered (fixed summation order).
 __global__ __launch_bounds__(kCtrSlots) void k_sum_slots(const unsigned long long* slots,
                                                          unsigned long long* ctr) {
-  __shared__ unsigned long long part[4][kCtrSlots / 64];
+  __shared__ unsigned long long part[5][kCtrSlots / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    unsigned long long x = slots[threadIdx.x * 4 + q];
+  for (int q = 0; q < 5; ++q) {
+    unsigned long long x = slots[threadIdx.x * kSlotW + q];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     if (lane == 0) part[q][wave] = x;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < 5) {
     unsigned long long t = 0;
     for (int w = 0; w < kCtrSlots / 64; ++w) t += part[threadIdx.x][w];
-    const int dst[4] = {0, 1, 4, 5};
+    const int dst[5] = {0, 1, 4, 5, 6};
     ctr[dst[threadIdx.x]] = t;
   }
 }

@@ -78,6 +78,7 @@ int make_view(const msgs_camera* cam, const msgs_render_opts* o, int n_levels, V
   v->lowpass = o->lowpass;
   for (int i = 0; i < 3; ++i) v->bg[i] = o->bg[i];
   v->selective = o->selective ? 1 : 0;
+  v->prefilter = o->no_prefilter ? 0 : 1;
   v->update_level = -1;
   if (o->update_range) {
     long long sc = 1;
@@ -126,7 +127,7 @@ int render_phase1(msgs_frame* f) {
   const bool even = radix_passes(0, 32) % 2 == 0;
   uint32_t* dv0 = nullptr;
   Carve keep;
-  keep.add(&f->ctr, (8 + 4 * kCtrSlots) * sizeof(unsigned long long));
+  keep.add(&f->ctr, (8 + kSlotW * kCtrSlots) * sizeof(unsigned long long));
   keep.add(&f->sel, n);
   keep.add(&f->count, n * 4);
   keep.add(&f->depthkey, n * 4);
@@ -156,7 +157,7 @@ int render_phase1(msgs_frame* f) {
   uint32_t* vin = even ? f->order : f->dvals_alt;
   uint32_t* valt = even ? f->dvals_alt : f->order;
   dv0 = vin;
-  launch_fill_u32((uint32_t*)f->ctr, 2 * (8 + 4 * kCtrSlots), 0u, st);
+  launch_fill_u32((uint32_t*)f->ctr, 2 * (8 + kSlotW * kCtrSlots), 0u, st);
   mark(f, 0);
   launch_project(f->scene->view, v, f->sel, f->count, f->depthkey, f->rec, f->rect, f->blk_vis,
                  f->ctr + 8, st);
@@ -241,6 +242,7 @@ void msgs_default_opts(msgs_render_opts* o) {
   o->near_z = 0.2f;
   o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
   o->profile = 0;
+  o->no_prefilter = 0;
 }
 
 int msgs_context_create(int device, size_t pool_bytes, msgs_context** out) {
@@ -616,7 +618,7 @@ int msgs_frame_stats(const msgs_frame* f, msgs_stats* out) {
   if (!f || !out) return fail(MSGS_E_INVALID, "null argument");
   int rc = frame_sync(f);
   if (rc != MSGS_OK) return rc;
-  unsigned long long h[6];
+  unsigned long long h[7];
   hipError_t e = hipMemcpy(h, f->ctr, sizeof h, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "stats readback");
   for (int i = 0; i < 12; ++i) out->stage_us[i] = 0.0f;
@@ -647,6 +649,7 @@ int msgs_frame_stats(const msgs_frame* f, msgs_stats* out) {
   }
   out->n_visits = (int64_t)h[4];
   out->n_evals = (int64_t)h[5];
+  out->n_prefiltered = (int64_t)h[6];
   out->n_gaussians = f->n;
   out->n_selected = (int64_t)h[0];
   out->n_visible = (int64_t)h[2];

@@ -15,6 +15,7 @@ namespace msgs {
 
 // counter slots per frame (spread per-block/per-wave counter atomics)
 constexpr int kCtrSlots = 256;
+constexpr int kSlotW = 8;  // counters per slot: selected, blends, visits, evals, prefiltered
 
 constexpr int kBlock = 256;   // threads per workgroup (4 wave64)
 constexpr int kTile = 16;     // tile edge in pixels (Sec. 3.1)
@@ -45,6 +46,7 @@ struct ViewParams {
   float bg[3];
   int selective;
   int update_level;      // level whose creation downscale equals this one, or -1
+  int prefilter;         // apply the conservative pre-splat coverage bound
 };
 
 // Projected record of a drawable Gaussian, three float4 per Gaussian index:

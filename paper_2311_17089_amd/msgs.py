@@ -41,7 +41,7 @@ class CameraC(C.Structure):
 class RenderOpts(C.Structure):
     _fields_ = [("downscale", C.c_int), ("selective", C.c_int), ("update_range", C.c_int),
                 ("lowpass", C.c_float), ("near_z", C.c_float), ("bg", C.c_float * 3),
-                ("profile", C.c_int)]
+                ("profile", C.c_int), ("no_prefilter", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -49,7 +49,7 @@ class Stats(C.Structure):
                 ("n_instances", C.c_int64), ("n_blends", C.c_int64), ("n_visits", C.c_int64),
                 ("n_evals", C.c_int64),
                 ("width", C.c_int), ("height", C.c_int), ("tiles_x", C.c_int), ("tiles_y", C.c_int),
-                ("stage_us", C.c_float * 12)]
+                ("stage_us", C.c_float * 12), ("n_prefiltered", C.c_int64)]
 
 
 class Grads(C.Structure):
@@ -145,9 +145,10 @@ def camera_c(cam) -> CameraC:
 
 
 def opts_c(downscale=1, selective=True, update_range=False, lowpass=0.3, near=0.2,
-           bg: Sequence[float] = (0.0, 0.0, 0.0), profile=False) -> RenderOpts:
+           bg: Sequence[float] = (0.0, 0.0, 0.0), profile=False, prefilter=True) -> RenderOpts:
     o = RenderOpts()
     o.profile = 1 if profile else 0
+    o.no_prefilter = 0 if prefilter else 1
     o.downscale = int(downscale)
     o.selective = 1 if selective else 0
     o.update_range = 1 if update_range else 0
@@ -272,7 +273,7 @@ class Frame:
 
 def render(ctx: Context, scene: DeviceScene, cam, downscale=1, selective=True,
            update_range=False, lowpass=0.3, near=0.2, bg=(0.0, 0.0, 0.0), keep_frame=False,
-           out: Optional[torch.Tensor] = None, stream=None, profile=False):
+           out: Optional[torch.Tensor] = None, stream=None, profile=False, prefilter=True):
     """Render one view; returns the image tensor [H_d, W_d, 3] (and the Frame
     when keep_frame)."""
     W, H = (cam.width // downscale, cam.height // downscale) if downscale >= 1 else (0, 0)
@@ -282,7 +283,7 @@ def render(ctx: Context, scene: DeviceScene, cam, downscale=1, selective=True,
     if W > 0 and H > 0:
         assert tuple(out.shape) == (H, W, 3), (tuple(out.shape), (H, W, 3))
     c = camera_c(cam)
-    o = opts_c(downscale, selective, update_range, lowpass, near, bg, profile)
+    o = opts_c(downscale, selective, update_range, lowpass, near, bg, profile, prefilter)
     fh = C.c_void_p()
     check(lib().msgs_render(ctx.h, scene.h, C.byref(c), C.byref(o), C.c_void_p(out.data_ptr()),
                             C.byref(fh) if keep_frame else None, C.c_void_p(_stream(stream))))

@@ -163,3 +163,35 @@ def test_invalid_arguments(ctx):
         M.render(ctx, dsc, cam, downscale=64, out=torch.empty(1, 1, 3, device="cuda"))
     assert e.value.code == M.E_INVALID
     dsc.close()
+
+
+def test_prefilter_is_exact(ctx):
+    # the conservative pre-splat bound changes no result: masks, keys, images
+    # and statistics are identical with it on and off; it does cull some
+    sc = G.make_scene([40000, 10000, 2500, 620], 61, 1, [-4.2 + 1.4 * l for l in range(4)],
+                      blob_fraction0=0.5)
+    cal = O.calibrate(sc, G.calibration_cameras(1061, 320, 240, 300.0))
+    cam = G.lookat_camera(G.sphere_poses(1, 61, 2.4, 3.2)[0], 320, 240, 300.0)
+    dsc = M.DeviceScene(ctx, cal)
+    culled = 0
+    for ds in (1, 4, 16):
+        for selective in (True, False):
+            outs = []
+            for pre in (True, False):
+                rgb, fr = M.render(ctx, dsc, cam, downscale=ds, selective=selective,
+                                   keep_frame=True, prefilter=pre)
+                st = fr.stats()
+                outs.append((rgb.cpu().numpy(), fr.selection(), fr.keys(), st))
+                fr.release()
+            (a, ma, ka, sa), (b, mb, kb, sb) = outs
+            np.testing.assert_array_equal(a, b)
+            np.testing.assert_array_equal(ma, mb)
+            np.testing.assert_array_equal(ka[0], kb[0])
+            np.testing.assert_array_equal(ka[1], kb[1])
+            assert sa["n_blends"] == sb["n_blends"] and sb["n_prefiltered"] == 0
+            if not selective:
+                assert sa["n_prefiltered"] == 0
+            culled += sa["n_prefiltered"]
+            assert sa["n_prefiltered"] <= cal.n - sa["n_selected"]
+    assert culled > 0
+    dsc.close()
