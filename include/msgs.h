@@ -115,6 +115,15 @@ typedef struct {
   int profile;
   int no_prefilter;  /* 1: skip the conservative pre-splat bound (results are
                         identical either way; for checks and measurement) */
+  long long instance_capacity; /* 0: exact mode, the tile-instance count is read
+                        back once per render (one host synchronisation) to
+                        size the tile lists.  > 0: fixed capacity, no host
+                        synchronisation and no allocation beyond the cached
+                        ones, so that the render (and its backward) can be
+                        captured in a HIP graph; if the frame needs more
+                        instances its image is incomplete and
+                        msgs_frame_stats returns MSGS_E_CAPACITY.  Not with
+                        profile = 1. */
 } msgs_render_opts;
 
 typedef struct {

@@ -139,7 +139,14 @@ void DeviceCache::free(msgs_context* c, void* p, hipStream_t st) {
   const size_t sz = it->second;
   impl->live_.erase(it);
   c->in_use -= sz;
-  hipEvent_t ev = impl->get_event();
+  // while the stream is captured into a graph no event is recorded: the block
+  // is then reusable on the same stream only
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (st && hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    cs = hipStreamCaptureStatusNone;
+  }
+  hipEvent_t ev = cs == hipStreamCaptureStatusNone ? impl->get_event() : nullptr;
   if (ev && hipEventRecord(ev, st) != hipSuccess) {
     (void)hipGetLastError();
     impl->events_.push_back(ev);

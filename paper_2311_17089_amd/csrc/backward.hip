@@ -279,12 +279,13 @@ __device__ __forceinline__ void store3(float* gsum, int64_t k, const float* s) {
 // emission order; those with more than kSmallSeg tiles are queued for
 // k_seg_big.
 __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int64_t n_vis,
+                                                      const uint32_t* d_nvis,
                                                       const uint32_t* count,
                                                       const uint32_t* emit_base,
                                                       const float* partial, const uint32_t* wmask,
                                                       float* gsum, uint32_t* big, uint32_t* nbig) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n_vis) return;
+  if (j >= n_vis || j >= (int64_t)*d_nvis) return;
   const uint32_t k = order[j];
   const uint32_t c = count[k];
   if (c > kSmallSeg) {
@@ -530,6 +531,7 @@ void launch_backward_chain(const BwdArgs& a, hipStream_t st) {
   if (n == 0) return;
   if (a.n_vis > 0) {
     hipLaunchKernelGGL(k_seg_small, dim3(grid_for(a.n_vis)), dim3(kBlock), 0, st, a.order, a.n_vis,
+                       a.d_nvis,
                        a.count, a.emit_base, a.partial, a.wmask, a.gsum, a.big, a.nbig);
     hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, a.partial,
                        a.wmask, a.gsum, a.big, a.nbig);

@@ -183,7 +183,8 @@ constexpr uint32_t kEmitSmall = 16;
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* order, const uint32_t* off,
                                                  const uint32_t* d_nvis, const uint32_t* count,
                                                  const uint2* rect, int Tx, uint32_t* tkeys,
-                                                 uint32_t* tvals, uint32_t* emit_base) {
+                                                 uint32_t* tvals, uint32_t* emit_base,
+                                                 uint32_t cap) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = j < (int64_t)*d_nvis;
@@ -203,8 +204,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* order, const ui
     for (int ty = yl; ty <= yh; ++ty) {
       const uint32_t row = (uint32_t)ty * (uint32_t)Tx;
       for (int tx = xl; tx <= xh; ++tx) {
-        tkeys[i] = row + (uint32_t)tx;
-        tvals[i] = k;
+        if (i < cap) {
+          tkeys[i] = row + (uint32_t)tx;
+          tvals[i] = k;
+        }
         ++i;
       }
     }
@@ -219,8 +222,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* order, const ui
     const uint32_t nx = xh - xl + 1;
     for (uint32_t li = lane; li < bc; li += 64) {
       const uint32_t dy = li / nx, dx = li - dy * nx;
-      tkeys[bb + li] = (yl + dy) * (uint32_t)Tx + xl + dx;
-      tvals[bb + li] = bk;
+      if (bb + li < cap) {
+        tkeys[bb + li] = (yl + dy) * (uint32_t)Tx + xl + dx;
+        tvals[bb + li] = bk;
+      }
     }
   }
 }
@@ -230,9 +235,11 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* p, int64_t n, uin
   if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* tkeys, uint32_t ninst,
-                                                   uint2* ranges) {
+// The instances of the list: *d_n when given (at most nmax), else nmax.
+__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* tkeys, const uint32_t* d_n,
+                                                   uint32_t nmax, uint2* ranges) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t ninst = d_n ? min(*d_n, nmax) : nmax;
   if (i >= ninst) return;
   const uint32_t t = tkeys[i];
   if (i == 0 || tkeys[i - 1] != t) ranges[t].x = i;
@@ -470,10 +477,19 @@ void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
 
 void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_nvis,
                  int64_t nmax, const uint32_t* count, const uint2* rect, int Tx, uint32_t* tkeys,
-                 uint32_t* tvals, uint32_t* emit_base, hipStream_t st) {
+                 uint32_t* tvals, uint32_t* emit_base, uint32_t cap, hipStream_t st) {
   if (nmax == 0) return;
   hipLaunchKernelGGL(k_emit, dim3(grid_for(nmax)), dim3(kBlock), 0, st, order, off, d_nvis, count,
-                     rect, Tx, tkeys, tvals, emit_base);
+                     rect, Tx, tkeys, tvals, emit_base, cap);
+}
+
+// Instances that fit: ctr[7] = min(ctr[3], cap) (fixed-capacity renders).
+__global__ void k_cap_clamp(unsigned long long* ctr, unsigned long long cap) {
+  if (threadIdx.x == 0) ctr[7] = ctr[3] < cap ? ctr[3] : cap;
+}
+
+void launch_cap_clamp(unsigned long long* ctr, unsigned long long cap, hipStream_t st) {
+  hipLaunchKernelGGL(k_cap_clamp, dim3(1), dim3(64), 0, st, ctr, cap);
 }
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
@@ -481,9 +497,11 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kBlock), 0, st, p, n, v);
 }
 
-void launch_ranges(const uint32_t* tkeys, uint32_t ninst, uint2* ranges, hipStream_t st) {
-  if (ninst == 0) return;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(ninst)), dim3(kBlock), 0, st, tkeys, ninst, ranges);
+void launch_ranges(const uint32_t* tkeys, const uint32_t* d_n, uint32_t nmax, uint2* ranges,
+                   hipStream_t st) {
+  if (nmax == 0) return;
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(nmax)), dim3(kBlock), 0, st, tkeys, d_n, nmax,
+                     ranges);
 }
 
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,

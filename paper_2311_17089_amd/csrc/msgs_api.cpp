@@ -202,14 +202,18 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   uint32_t* v1 = even ? vb : va;
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
   mark(f, 4);
-  launch_emit(f->order, f->off_d, d_nvis, n, f->count, f->rect, v.Tx, k0, v0, f->emit_base, st);
+  // fixed capacity: the instance count stays on the device (ctr[7] = the
+  // instances that fit); emission, sort and ranges never pass the capacity
+  const uint32_t* d_inst = f->capacity ? (const uint32_t*)&f->ctr[7] : nullptr;
+  launch_emit(f->order, f->off_d, d_nvis, n, f->count, f->rect, v.Tx, k0, v0, f->emit_base,
+              f->capacity ? (uint32_t)I : 0xFFFFFFFFu, st);
   mark(f, 5);
-  radix_sort_pairs(k0, v0, k1, v1, nullptr, I, 0, bits, stmp, st);
+  radix_sort_pairs(k0, v0, k1, v1, d_inst, I, 0, bits, stmp, st);
   mark(f, 6);
   f->tkeys = ka;
   f->tvals = va;
   launch_fill_u32((uint32_t*)f->ranges, (int64_t)ntile * 2, 0u, st);
-  launch_ranges(f->tkeys, (uint32_t)I, f->ranges, st);
+  launch_ranges(f->tkeys, d_inst, (uint32_t)I, f->ranges, st);
   mark(f, 7);
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
                f->ctr + 8, st);
@@ -243,6 +247,7 @@ void msgs_default_opts(msgs_render_opts* o) {
   o->bg[0] = o->bg[1] = o->bg[2] = 0.0f;
   o->profile = 0;
   o->no_prefilter = 0;
+  o->instance_capacity = 0;
 }
 
 int msgs_context_create(int device, size_t pool_bytes, msgs_context** out) {
@@ -484,9 +489,14 @@ int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
   ViewParams v;
   int rc = make_view(cam, &o, s->view.n_levels, &v);
   if (rc != MSGS_OK) return rc;
+  if (o.instance_capacity < 0 || o.instance_capacity >= (1ll << 32))
+    return fail(MSGS_E_INVALID, "instance_capacity must be in [0, 2^32)");
+  if (o.instance_capacity && o.profile)
+    return fail(MSGS_E_INVALID, "profiling needs the exact (instance_capacity = 0) mode");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   msgs_frame* f = new msgs_frame();
+  f->capacity = o.instance_capacity;
   f->ctx = c;
   f->scene = s;
   f->st = (hipStream_t)stream;
@@ -506,7 +516,12 @@ int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
   }
   rc = render_phase1(f);
   if (rc == MSGS_OK && t_waiter) t_waiter->on_admitted();
-  if (rc == MSGS_OK) {
+  if (rc == MSGS_OK && f->capacity) {
+    // no host synchronisation: tile lists sized by the capacity
+    f->n_vis = f->n;
+    f->n_inst = f->capacity;
+    launch_cap_clamp(f->ctr, (unsigned long long)f->capacity, f->st);
+  } else if (rc == MSGS_OK) {
     unsigned long long* hp = pinned_slot();
     if (!hp) {
       rc = fail(MSGS_E_DEVICE, "pinned host memory unavailable");
@@ -562,6 +577,7 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   a.count = f->count;
   a.order = f->order;
   a.n_vis = f->n_vis;
+  a.d_nvis = (const uint32_t*)&f->ctr[2];
   a.T_final = f->T_final;
   a.n_last = f->n_last;
   a.dL_drgb = dL_drgb;
@@ -659,6 +675,10 @@ int msgs_frame_stats(const msgs_frame* f, msgs_stats* out) {
   out->height = f->v.H;
   out->tiles_x = f->v.Tx;
   out->tiles_y = f->v.Ty;
+  if (f->capacity && (int64_t)h[3] > f->capacity)
+    return fail(MSGS_E_CAPACITY, "the frame needed " + std::to_string(h[3]) +
+                                     " tile instances, capacity " + std::to_string(f->capacity) +
+                                     ": its image and state are incomplete");
   return MSGS_OK;
 }
 
@@ -676,12 +696,19 @@ int msgs_frame_get_selection(const msgs_frame* f, uint8_t* mask) {
 int msgs_frame_get_keys(const msgs_frame* f, uint64_t* keys, uint32_t* vals, size_t cap,
                         size_t* nout) {
   if (!f || !nout) return fail(MSGS_E_INVALID, "null argument");
-  *nout = (size_t)f->n_inst;
-  if (cap < (size_t)f->n_inst || f->n_inst == 0) return MSGS_OK;
-  if (!keys || !vals) return fail(MSGS_E_INVALID, "null output arrays");
   int rc = frame_sync(f);
   if (rc != MSGS_OK) return rc;
-  std::vector<uint32_t> tk((size_t)f->n_inst), dk((size_t)f->n);
+  size_t ni = (size_t)f->n_inst;
+  if (f->capacity) {  // the list holds the instances that fit
+    unsigned long long h = 0;
+    hipError_t e0 = hipMemcpy(&h, &f->ctr[7], sizeof h, hipMemcpyDeviceToHost);
+    if (e0 != hipSuccess) return hip_fail(e0, "instance count readback");
+    ni = (size_t)h;
+  }
+  *nout = ni;
+  if (cap < ni || ni == 0) return MSGS_OK;
+  if (!keys || !vals) return fail(MSGS_E_INVALID, "null output arrays");
+  std::vector<uint32_t> tk(ni), dk((size_t)f->n);
   hipError_t e = hipMemcpy(tk.data(), f->tkeys, tk.size() * 4, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(vals, f->tvals, tk.size() * 4, hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(dk.data(), f->depthkey, dk.size() * 4, hipMemcpyDeviceToHost);

@@ -64,13 +64,15 @@ struct msgs_frame {
   int64_t n = 0;
   int64_t n_vis = 0;
   int64_t n_inst = 0;
+  int64_t capacity = 0;               // fixed tile-list capacity (0: exact, host-sized)
   std::vector<void*> blocks;          // allocations owned by the frame
   // profiling events (opts.profile): forward stage boundaries 0..8, backward 9..11
   bool profile = false;
   hipEvent_t ev[13] = {};
   bool bwd_recorded = false;
   // kept for the backward pass and the getters
-  unsigned long long* ctr = nullptr;   // [0] selected [1] blends [2] visible [3] instances [4] visits [5] evaluations
+  unsigned long long* ctr = nullptr;   // [0] selected [1] blends [2] visible [3] instances [4] visits
+                                       // [5] evaluations [6] prefiltered [7] instances that fit
   uint8_t* sel = nullptr;
   uint32_t* count = nullptr;
   uint32_t* depthkey = nullptr;

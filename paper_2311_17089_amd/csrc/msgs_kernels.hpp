@@ -17,9 +17,11 @@ void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
                     const uint32_t* blk_off, uint32_t* keys, uint32_t* vals, hipStream_t st);
 void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_nvis,
                  int64_t nmax, const uint32_t* count, const uint2* rect, int Tx, uint32_t* tkeys,
-                 uint32_t* tvals, uint32_t* emit_base, hipStream_t st);
+                 uint32_t* tvals, uint32_t* emit_base, uint32_t cap, hipStream_t st);
+void launch_cap_clamp(unsigned long long* ctr, unsigned long long cap, hipStream_t st);
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
-void launch_ranges(const uint32_t* tkeys, uint32_t ninst, uint2* ranges, hipStream_t st);
+void launch_ranges(const uint32_t* tkeys, const uint32_t* d_n, uint32_t nmax, uint2* ranges,
+                   hipStream_t st);
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
                   unsigned long long* slots, hipStream_t st);
@@ -52,7 +54,8 @@ struct BwdArgs {
   const uint32_t* emit_base;
   const uint32_t* count;
   const uint32_t* order;    // drawable Gaussians in depth (emission) order
-  int64_t n_vis;
+  int64_t n_vis;            // upper bound of the drawable count
+  const uint32_t* d_nvis;   // drawable count on the device
   const float* T_final;
   const uint32_t* n_last;
   const float* dL_drgb;

@@ -41,7 +41,8 @@ class CameraC(C.Structure):
 class RenderOpts(C.Structure):
     _fields_ = [("downscale", C.c_int), ("selective", C.c_int), ("update_range", C.c_int),
                 ("lowpass", C.c_float), ("near_z", C.c_float), ("bg", C.c_float * 3),
-                ("profile", C.c_int), ("no_prefilter", C.c_int)]
+                ("profile", C.c_int), ("no_prefilter", C.c_int),
+                ("instance_capacity", C.c_longlong)]
 
 
 class Stats(C.Structure):
@@ -145,8 +146,10 @@ def camera_c(cam) -> CameraC:
 
 
 def opts_c(downscale=1, selective=True, update_range=False, lowpass=0.3, near=0.2,
-           bg: Sequence[float] = (0.0, 0.0, 0.0), profile=False, prefilter=True) -> RenderOpts:
+           bg: Sequence[float] = (0.0, 0.0, 0.0), profile=False, prefilter=True,
+           capacity=0) -> RenderOpts:
     o = RenderOpts()
+    o.instance_capacity = int(capacity)
     o.profile = 1 if profile else 0
     o.no_prefilter = 0 if prefilter else 1
     o.downscale = int(downscale)
@@ -273,7 +276,8 @@ class Frame:
 
 def render(ctx: Context, scene: DeviceScene, cam, downscale=1, selective=True,
            update_range=False, lowpass=0.3, near=0.2, bg=(0.0, 0.0, 0.0), keep_frame=False,
-           out: Optional[torch.Tensor] = None, stream=None, profile=False, prefilter=True):
+           out: Optional[torch.Tensor] = None, stream=None, profile=False, prefilter=True,
+           capacity=0):
     """Render one view; returns the image tensor [H_d, W_d, 3] (and the Frame
     when keep_frame)."""
     W, H = (cam.width // downscale, cam.height // downscale) if downscale >= 1 else (0, 0)
@@ -283,7 +287,7 @@ def render(ctx: Context, scene: DeviceScene, cam, downscale=1, selective=True,
     if W > 0 and H > 0:
         assert tuple(out.shape) == (H, W, 3), (tuple(out.shape), (H, W, 3))
     c = camera_c(cam)
-    o = opts_c(downscale, selective, update_range, lowpass, near, bg, profile, prefilter)
+    o = opts_c(downscale, selective, update_range, lowpass, near, bg, profile, prefilter, capacity)
     fh = C.c_void_p()
     check(lib().msgs_render(ctx.h, scene.h, C.byref(c), C.byref(o), C.c_void_p(out.data_ptr()),
                             C.byref(fh) if keep_frame else None, C.c_void_p(_stream(stream))))

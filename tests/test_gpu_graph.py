@@ -1,0 +1,138 @@
+"""Fixed-capacity renders and a training step captured in a HIP graph (needs
+an MI355X).  A fixed tile-instance capacity removes the render's only host
+synchronisation, so forward and backward can be captured; results must equal
+the exact mode bit for bit, overflow must be reported, and every replay of the
+captured step must reproduce the eager step."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2311_17089_amd import msgs as M
+from paper_2311_17089_amd import scenegen as G
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("means", "scales", "quats", "opacity", "sh")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _scene(ctx):
+    sc = G.make_scene([40000, 10000, 2500, 620], 71, 2, [-4.2 + 1.4 * l for l in range(4)],
+                      blob_fraction0=0.5)
+    dsc = M.DeviceScene(ctx, sc)
+    M.calibrate(ctx, dsc, G.calibration_cameras(1071, 320, 240, 300.0))
+    return dsc
+
+
+def _views():
+    poses = G.sphere_poses(4, 71, 2.4, 3.4)
+    return [(G.lookat_camera(poses[i], 320, 240, 300.0), 2 ** i) for i in range(4)]
+
+
+def test_fixed_capacity_matches_exact_and_reports_overflow():
+    ctx = M.Context(0)
+    dsc = _scene(ctx)
+    cam, d = _views()[0]
+    dl = torch.randn((240 // d, 320 // d, 3), generator=torch.Generator().manual_seed(3)).cuda()
+    rgb0, f0 = M.render(ctx, dsc, cam, downscale=d, keep_frame=True)
+    st0 = f0.stats()
+    g0 = M.render_backward(ctx, f0, dl)
+    I = st0["n_instances"]
+    for cap in (I, 2 * I + 7):
+        rgb1, f1 = M.render(ctx, dsc, cam, downscale=d, keep_frame=True, capacity=cap)
+        st1 = f1.stats()
+        g1 = M.render_backward(ctx, f1, dl)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(rgb0.cpu().numpy(), rgb1.cpu().numpy())
+        for k in ("n_selected", "n_visible", "n_instances", "n_blends", "n_visits"):
+            assert st0[k] == st1[k], k
+        for a, b in zip(f0.keys(), f1.keys()):
+            np.testing.assert_array_equal(a, b)
+        for a, b in zip(f0.state(), f1.state()):
+            np.testing.assert_array_equal(a, b)
+        for k in NAMES:
+            np.testing.assert_array_equal(g0[k].cpu().numpy(), g1[k].cpu().numpy())
+        f1.release()
+    # too small a capacity: the frame completes without fault and says so
+    _, f2 = M.render(ctx, dsc, cam, downscale=d, keep_frame=True, capacity=I // 2)
+    with pytest.raises(M.MsgsError) as e:
+        f2.stats()
+    assert e.value.code == M.E_CAPACITY
+    f2.release()
+    f0.release()
+    dsc.close()
+
+
+def test_captured_training_step_replays_exactly():
+    ctx = M.Context(0)
+    dsc = _scene(ctx)
+    views = _views()
+    dls = [torch.randn((240 // d, 320 // d, 3), generator=torch.Generator().manual_seed(10 + i))
+           .cuda() * 1e-3 for i, (_, d) in enumerate(views)]
+    caps = []
+    for cam, d in views:
+        _, fr = M.render(ctx, dsc, cam, downscale=d, keep_frame=True)
+        caps.append(int(fr.stats()["n_instances"] * 1.25) + 64)
+        fr.release()
+    grads = {k: torch.zeros_like(dsc.t[k]) for k in NAMES}
+    zeros = {k: torch.zeros_like(dsc.t[k]) for k in NAMES}
+    outs = [torch.empty((240 // d, 320 // d, 3), device="cuda") for _, d in views]
+    frames = []
+
+    def step():
+        for k in NAMES:
+            grads[k].copy_(zeros[k])
+        fs = []
+        for (cam, d), dl, cap, o in zip(views, dls, caps, outs):
+            _, fr = M.render(ctx, dsc, cam, downscale=d, keep_frame=True, capacity=cap, out=o)
+            M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
+            fs.append(fr)
+        return fs
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):  # eager runs on the capture stream warm the allocator up
+            for fr in step():
+                fr.release()
+        ref_frames = step()
+    torch.cuda.synchronize()
+    for fr in ref_frames:
+        fr.stats()  # no overflow
+    ref_g = {k: v.cpu().numpy() for k, v in grads.items()}
+    ref_img = [o.cpu().numpy() for o in outs]
+    for fr in ref_frames:
+        fr.release()
+    torch.cuda.synchronize()
+
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        frames = step()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for k in NAMES:
+            grads[k].fill_(7.0)
+        for o in outs:
+            o.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in NAMES:
+            np.testing.assert_array_equal(grads[k].cpu().numpy(), ref_g[k])
+        for o, r in zip(outs, ref_img):
+            np.testing.assert_array_equal(o.cpu().numpy(), r)
+        # unrelated eager work between replays, on another context's memory
+        other = M.Context(0)
+        o2 = M.DeviceScene(other, G.make_scene([3000], 5 + rep, 0, [-3.0]))
+        M.render(other, o2, views[0][0], downscale=2)
+        torch.cuda.synchronize()
+        o2.close()
+    _say(f"  captured {len(views)} views, 3 replays identical to the eager step")
+    del g
+    torch.cuda.synchronize()
+    for fr in frames:
+        fr.release()
+    dsc.close()
