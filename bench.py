@@ -166,7 +166,10 @@ def training_step(M, G, steps=5, warmup=2):
     (seeded poses on a sphere of radius 2-12), one at each downscale 1, 2, ...,
     128 of 1920x1080, each rendered with the range update on and its backward
     accumulated into one set of gradient planes, all on one stream.  dL/dRGB is
-    a fixed seeded tensor per view.  Returns step time and blends per second."""
+    a fixed seeded tensor per view.  Timed twice: eagerly (exact tile lists,
+    one host synchronisation per view) and as one captured HIP graph (fixed
+    tile-list capacities of 1.25x the eager counts, no host synchronisation).
+    Returns step times and blends per second."""
     import numpy as np
     import torch
     ctx = M.Context(0)
@@ -177,35 +180,78 @@ def training_step(M, G, steps=5, warmup=2):
     views = [(G.lookat_camera(poses[i], 1920, 1080, 2250.0), 2 ** i) for i in range(8)]
     dls = [torch.randn((1080 // d, 1920 // d, 3), generator=torch.Generator().manual_seed(900 + i))
            .cuda() * 1e-6 for i, (_, d) in enumerate(views)]
+    outs = [torch.empty((1080 // d, 1920 // d, 3), device="cuda") for _, d in views]
     names = ("means", "scales", "quats", "opacity", "sh")
     grads = {k: torch.zeros_like(dsc.t[k]) for k in names}
-    blends = [0]
+    zeros = {k: torch.zeros_like(dsc.t[k]) for k in names}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    caps = [0] * len(views)
 
-    def step(count=False):
-        for g in grads.values():
-            g.zero_()
-        for (cam, d), dl in zip(views, dls):
-            _, fr = M.render(ctx, dsc, cam, downscale=d, update_range=True, keep_frame=True)
+    def step(capacity=False, keep=False):
+        for k in names:
+            grads[k].copy_(zeros[k])
+        frames, blends = [], 0
+        for i, ((cam, d), dl) in enumerate(zip(views, dls)):
+            _, fr = M.render(ctx, dsc, cam, downscale=d, update_range=True, keep_frame=True,
+                             out=outs[i], capacity=caps[i] if capacity else 0)
             M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
-            if count:
-                blends[0] += fr.stats()["n_blends"]
+            frames.append(fr)
+        if keep:
+            return frames
+        for fr in frames:
             fr.release()
+        return []
 
-    for _ in range(warmup):
-        step()
+    with torch.cuda.stream(side):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        fr0 = step(keep=True)
+        st0 = [f.stats() for f in fr0]
+        blends = sum(s["n_blends"] for s in st0)
+        for i, s in enumerate(st0):
+            caps[i] = int(s["n_instances"] * 1.25) + 1024
+        for f in fr0:
+            f.release()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t_eager = (time.perf_counter() - t0) / steps
+        # capture: warm the allocator on this stream with the same capacities
+        for _ in range(2):
+            step(capacity=True)
+        torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        frames = step(capacity=True, keep=True)
     torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    overflow = 0
+    for f in frames:
+        try:
+            f.stats()
+        except M.MsgsError:
+            overflow += 1
     t0 = time.perf_counter()
     for _ in range(steps):
-        step()
+        g.replay()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    step(count=True)
+    t_graph = (time.perf_counter() - t0) / steps
+    del g
     torch.cuda.synchronize()
+    for f in frames:
+        f.release()
     dsc.close()
     return {"workload": "6M Gaussians over 5 levels (SH degree 3), 8 views at 1920x1080 / "
                         "{1,2,...,128}, range update on, gradients accumulated",
-            "ms_per_step": dt * 1e3, "blends_per_step": blends[0],
-            "blends_per_s": blends[0] / dt, "steps": steps, "graph": False}
+            "ms_per_step_eager": t_eager * 1e3, "ms_per_step_graph": t_graph * 1e3,
+            "blends_per_step": blends, "blends_per_s_eager": blends / t_eager,
+            "blends_per_s_graph": blends / t_graph, "steps": steps,
+            "graph_capacity_overflows": overflow}
 
 
 def traffic_for(kernel, launch):
