@@ -6,8 +6,8 @@
  * (Yan, Low, Chen, Lee; CVPR 2024).  A scene of 3D Gaussians, each tagged with
  * a level of detail, is rendered at any resolution by the SelectiveRender
  * procedure (Alg. 2): pixel coverage of every Gaussian (Sec. 4.1), the
- * selection condition with the finest/coarsest exemptions (Sec. 4.2), an
- * optional range update of S^max/S^min (Sec. 4.2), then the tile rasteriser of
+ * selection condition with the finest/coarsest exemptions (Sec. 4.1 on selective rendering), an
+ * optional range update of S^max/S^min (Sec. 4.1 on selective rendering), then the tile rasteriser of
  * Sec. 3.1 (EWA splatting, 16x16 tiles, depth-sorted front-to-back blending).
  * The backward pass is the exact adjoint of that forward for fixed discrete
  * decisions.
@@ -53,8 +53,9 @@ typedef struct msgs_scene msgs_scene;
 typedef struct msgs_frame msgs_frame;
 typedef struct msgs_server msgs_server;
 
-/* Scene description (Sec. 3.1 Gaussian record; Sec. 4.1 level; Sec. 4.2 stored
- * coverage range).  All arrays have n entries per component:
+/* Scene description (Sec. 3.1 Gaussian record; Sec. 4.1: the level and the
+ * stored coverage range of selective rendering).  All arrays have n entries
+ * per component:
  *   means[3][n]     centres (world units)
  *   scales[3][n]    per-axis standard deviations, linear, > 0
  *   quats[4][n]     rotation quaternion (w, x, y, z), any non-zero length
@@ -91,11 +92,11 @@ typedef struct {
 
 /* Render options.
  *   downscale    per-side factor d >= 1
- *   selective    1: apply the selection condition of Sec. 4.2 with the level
+ *   selective    1: apply the selection condition of Sec. 4.1 on selective rendering with the level
  *                exemptions; 0: render every Gaussian in front of the camera
  *                (single-scale rendering)
  *   update_range 1: after selection, apply the range update (decays 0.95 and
- *                1.05, Sec. 4.2) to Gaussians in front of the camera whose
+ *                1.05, Sec. 4.1 on selective rendering) to Gaussians in front of the camera whose
  *                level l satisfies 4^l == downscale; writes the scene's
  *                s_max/s_min in place
  *   lowpass      screen-space dilation h (px^2) added to the projected

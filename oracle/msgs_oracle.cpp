@@ -13,9 +13,9 @@
 //   * pixel coverage S_k: the shorter of the horizontal and vertical chords
 //     through the centre of the level set sigma*G = sigma_T, sigma_T = 1/255
 //     (Sec. 4.1, pixel-coverage paragraph and its figure);
-//   * the selection rule of Sec. 4.2 (the inequality on S/S^max, S/S^min and
+//   * the selection rule of Sec. 4.1 on selective rendering (the inequality on S/S^max, S/S^min and
 //     S_T = 2 px) with the finest/coarsest-level exemptions, and the range
-//     update with decay factors 0.95 / 1.05 (Sec. 4.2, Alg. 2);
+//     update with decay factors 0.95 / 1.05 (Sec. 4.1 on selective rendering, Alg. 2);
 //   * tile binning into 16x16 tiles and the depth order (Sec. 3.1);
 //   * front-to-back alpha compositing (Sec. 3.1/3.2), by BRUTE FORCE: every
 //     pixel visits every drawable Gaussian in depth order, with no tiles.
@@ -629,7 +629,7 @@ int64_t or_trace(const or_scene* s, const or_camera* c, const or_opts* o, int64_
   return total;
 }
 
-// Range update at this camera (Sec. 4.2): for Gaussians in front of the camera
+// Range update at this camera (Sec. 4.1 on selective rendering): for Gaussians in front of the camera
 // whose level l has creation downscale 4^l equal to the render downscale,
 // S^max <- max(0.95 S^max, S) and S^min <- min(1.05 S^min, S).  s_max/s_min
 // are updated in place in the caller's arrays (the scene's own pointers are

@@ -2,7 +2,7 @@
 //
 //  k_project   per Gaussian: EWA projection (Sec. 3.1, dilated kernel of
 //              Sec. 3.2), pixel coverage (Sec. 4.1), selection with level
-//              exemptions and the optional range update (Sec. 4.2, Alg. 2),
+//              exemptions and the optional range update (Sec. 4.1 on selective rendering, Alg. 2),
 //              conic, conservative tile rectangle, SH colour.  One thread per
 //              Gaussian over planar SoA loads; block counts of drawable
 //              Gaussians feed the order-preserving compaction.

@@ -10,7 +10,7 @@ quaternion, a density (opacity) and colour, here spherical-harmonic features
 (Supplementary, average pooling).  Each Gaussian carries a level tag (Sec. 4.1:
 four levels for 1x/4x/16x/64x downsampling), stored 0-based with level 0 the
 finest, and the stored pixel-coverage range S^max/S^min read by selective
-rendering (Sec. 4.2).
+rendering (Sec. 4.1 on selective rendering).
 
 Layout (planar fp32, one plane per component, length n each):
   means  [3][n]  x, y, z

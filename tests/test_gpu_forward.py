@@ -150,6 +150,11 @@ def test_edge_cases(ctx):
     # a 1x1 frame
     sc = G.make_scene([500], 4, 0, [-2.0])
     check_frame(ctx, sc, cam, 30)
+    # degenerate covariances: two of the three scales vanish (rank-one Sigma,
+    # zero determinant before the low-pass dilation)
+    sc = G.make_scene([500], 6, 0, [-3.0])
+    sc.scales[1:] = 1e-20
+    check_frame(ctx, sc, cam, 1)
 
 
 def test_invalid_arguments(ctx):

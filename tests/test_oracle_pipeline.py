@@ -129,7 +129,7 @@ def _sel_case(S_target_px, level, n_levels, smax, smin):
 
 
 @pytest.mark.parametrize("S,level,L,rmax,rmin,expect", [
-    # (coverage, level, levels, S/S^max, S/S^min, selected?)  Sec. 4.2 selection rule
+    # (coverage, level, levels, S/S^max, S/S^min, selected?)  Sec. 4.1 on selective rendering selection rule
     (1.2, 1, 3, 1.4, 1.0, True),    # both ratios inside the band
     (1.2, 1, 3, 1.6, 1.0, False),   # too large relative to S^max
     (1.2, 0, 3, 1.6, 1.0, True),    # finest level is never filtered as too large
