@@ -249,7 +249,8 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   for (int i = 0; i < ITEMS; ++i) k_[i] = i * 64 + lane < remw ? kin_w[i * 64 + lane] : 0u;
   // global start of every digit: exclusive scan of the digit totals
   uint32_t htot;
-  const uint32_t gs = block_excl_scan(hist[threadIdx.x], wtot, htot);
+  const uint32_t hd = hist[threadIdx.x];
+  const uint32_t gs = block_excl_scan(hd, wtot, htot);
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const bool valid = i * 64 + lane < remw;
@@ -283,8 +284,11 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
     cnt[w][d] = bt;
     bt += c;
   }
+  // a digit absent from the whole input has no status traffic at all: no
+  // workgroup publishes or reads it (all see the same histogram)
+  const bool used = hd != 0u;
   unsigned long long* st = status + t * kRadix + d;
-  st_status(st, (t == 0 ? kFlagP : kFlagA) | bt);
+  if (used) st_status(st, (t == 0 ? kFlagP : kFlagA) | bt);
   uint32_t tot;
   ldig[d] = block_excl_scan(bt, wtot, tot);
   __syncthreads();
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) v_[i] = i * 64 + lane < remw ? vin_w[i * 64 + lane] : 0u;
   unsigned long long excl = 0;
-  if (t > 0) {
+  if (t > 0 && used) {
     excl = look_back<4>(status + d, kRadix, t);
     st_status(st, kFlagP | (excl + bt));
   }
