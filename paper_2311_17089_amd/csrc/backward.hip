@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       s0[threadIdx.x] = n0;
       s1[threadIdx.x] = n1;
       s2[threadIdx.x] = n2;
-      qm = quad_mask(n0.x, n0.y, n2.z, n2.w, x0, y0);
+      qm = quad_mask_exact(n0.x, n0.y, n2.z, n2.w, n0.z, n0.w, n1.x, -n1.z, x0, y0);
       // a quadrant skips the instances at or past its last contributor
       const uint32_t pos_t = hi - 1 - threadIdx.x - rg.x;
 #pragma unroll

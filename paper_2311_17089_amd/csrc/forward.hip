@@ -313,7 +313,8 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
   }
   for (uint32_t c0 = rg.x; c0 < rg.y && __any(!done); c0 += 64) {
     const bool hit = have && !(n0.x + n2.z < bx0 || n0.x - n2.z > bx1 || n0.y + n2.w < by0 ||
-                               n0.y - n2.w > by1);
+                               n0.y - n2.w > by1) &&
+                     level_set_meets_box(n0.x, n0.y, n0.z, n0.w, n1.x, -n1.z, bx0, bx1, by0, by1);
     const unsigned long long m = __ballot(hit);
     const int nl = __popcll(m);
     if (hit) {

@@ -283,6 +283,32 @@ __device__ __forceinline__ float coverage(float V11, float V12, float V22, bool 
 // Bit w of the result is set when the conservative level-set box [u +- e] of
 // an instance reaches a pixel centre of quadrant w (8x8 pixels at (qx, qy) +
 // (w & 1, w >> 1) * 8) of the 16x16 tile whose first pixel is (x0, y0).
+// Whether the level set of a Gaussian (conic a, b, c; centre u; threshold lq)
+// can reach the box [x0, x1] x [y0, y1] of pixel centres: the minimum of the
+// quadratic form Q(d) = a dx^2 + 2 b dx dy + c dy^2 over the box (zero when the
+// centre is inside it, else the least of the four edge minima, each a clamped
+// one-dimensional quadratic) against 2 lq, with a relative margin of 1e-3 and
+// an absolute one of 1e-6 over the fp32 rounding of the compositing's power.
+// Where this is false no pixel of the box can take the Gaussian (power < -lq),
+// so culling with it changes no result.
+__device__ __forceinline__ bool level_set_meets_box(float ux, float uy, float a, float b, float c,
+                                                    float lq, float x0, float x1, float y0,
+                                                    float y1) {
+  const float l = x0 - ux, r = x1 - ux, lo = y0 - uy, hi = y1 - uy;
+  if (l <= 0.0f && r >= 0.0f && lo <= 0.0f && hi >= 0.0f) return true;
+  const float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
+  auto on_x = [&](float X) {  // edge dx = X, dy in [lo, hi]
+    const float y = fminf(fmaxf(-b * X * ic, lo), hi);
+    return a * X * X + 2.0f * b * X * y + c * y * y;
+  };
+  auto on_y = [&](float Y) {  // edge dy = Y, dx in [l, r]
+    const float x = fminf(fmaxf(-b * Y * ia, l), r);
+    return a * x * x + 2.0f * b * x * Y + c * Y * Y;
+  };
+  const float q = fminf(fminf(on_x(l), on_x(r)), fminf(on_y(lo), on_y(hi)));
+  return q <= 2.0f * lq * 1.001f + 1e-6f;
+}
+
 __device__ __forceinline__ uint32_t quad_mask(float ux, float uy, float ex, float ey, int x0,
                                               int y0) {
   uint32_t m = 0;
@@ -292,6 +318,21 @@ __device__ __forceinline__ uint32_t quad_mask(float ux, float uy, float ex, floa
     const float by0 = (float)(y0 + (w >> 1) * 8) + 0.5f, by1 = by0 + 7.0f;
     const bool miss = ux + ex < bx0 || ux - ex > bx1 || uy + ey < by0 || uy - ey > by1;
     m |= miss ? 0u : (1u << w);
+  }
+  return m;
+}
+
+// quad_mask refined by the level-set test (conic a, b, c; threshold lq).
+__device__ __forceinline__ uint32_t quad_mask_exact(float ux, float uy, float ex, float ey,
+                                                    float a, float b, float c, float lq, int x0,
+                                                    int y0) {
+  uint32_t m = quad_mask(ux, uy, ex, ey, x0, y0);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (!((m >> w) & 1u)) continue;
+    const float bx0 = (float)(x0 + (w & 1) * 8) + 0.5f, bx1 = bx0 + 7.0f;
+    const float by0 = (float)(y0 + (w >> 1) * 8) + 0.5f, by1 = by0 + 7.0f;
+    if (!level_set_meets_box(ux, uy, a, b, c, lq, bx0, bx1, by0, by1)) m &= ~(1u << w);
   }
   return m;
 }
