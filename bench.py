@@ -164,11 +164,12 @@ def serving_replay(M, G, n_req=512, rate_hz=200.0, inflight=4, selective=True):
 def training_step(M, G, steps=5, warmup=2):
     """Multi-view training step on the 6M-Gaussian, 5-level scene: 8 views
     (seeded poses on a sphere of radius 2-12), one at each downscale 1, 2, ...,
-    128 of 1920x1080, each rendered with the range update on and its backward
-    accumulated into one set of gradient planes, all on one stream.  dL/dRGB is
-    a fixed seeded tensor per view.  Timed twice: eagerly (exact tile lists,
-    one host synchronisation per view) and as one captured HIP graph (fixed
-    tile-list capacities of 1.25x the eager counts, no host synchronisation).
+    128 of 1920x1080, each rendered with the range update on, then one
+    multi-view backward into one set of gradient planes, all on one stream.
+    dL/dRGB is a fixed seeded tensor per view.  Timed eagerly (exact tile
+    lists, one host synchronisation per view; also with one backward call per
+    view, for comparison) and as one captured HIP graph (fixed tile-list
+    capacities of 1.25x the eager counts, no host synchronisation).
     Returns step times and blends per second."""
     import numpy as np
     import torch
@@ -188,15 +189,19 @@ def training_step(M, G, steps=5, warmup=2):
     side.wait_stream(torch.cuda.current_stream())
     caps = [0] * len(views)
 
-    def step(capacity=False, keep=False):
-        for k in names:
-            grads[k].copy_(zeros[k])
-        frames, blends = [], 0
+    def step(capacity=False, keep=False, batched=True):
+        frames = []
+        if not batched:
+            for k in names:
+                grads[k].copy_(zeros[k])
         for i, ((cam, d), dl) in enumerate(zip(views, dls)):
             _, fr = M.render(ctx, dsc, cam, downscale=d, update_range=True, keep_frame=True,
                              out=outs[i], capacity=caps[i] if capacity else 0)
-            M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
+            if not batched:
+                M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
             frames.append(fr)
+        if batched:
+            M.render_backward_views(ctx, frames, dls, grads=grads)
         if keep:
             return frames
         for fr in frames:
@@ -215,11 +220,15 @@ def training_step(M, G, steps=5, warmup=2):
         for f in fr0:
             f.release()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step()
-        torch.cuda.synchronize()
-        t_eager = (time.perf_counter() - t0) / steps
+        t_eager = {}
+        for batched in (False, True):
+            step(batched=batched)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step(batched=batched)
+            torch.cuda.synchronize()
+            t_eager[batched] = (time.perf_counter() - t0) / steps
         # capture: warm the allocator on this stream with the same capacities
         for _ in range(2):
             step(capacity=True)
@@ -248,8 +257,9 @@ def training_step(M, G, steps=5, warmup=2):
     dsc.close()
     return {"workload": "6M Gaussians over 5 levels (SH degree 3), 8 views at 1920x1080 / "
                         "{1,2,...,128}, range update on, gradients accumulated",
-            "ms_per_step_eager": t_eager * 1e3, "ms_per_step_graph": t_graph * 1e3,
-            "blends_per_step": blends, "blends_per_s_eager": blends / t_eager,
+            "ms_per_step_eager": t_eager[True] * 1e3, "ms_per_step_graph": t_graph * 1e3,
+            "ms_per_step_eager_backward_per_view": t_eager[False] * 1e3,
+            "blends_per_step": blends, "blends_per_s_eager": blends / t_eager[True],
             "blends_per_s_graph": blends / t_graph, "steps": steps,
             "graph_capacity_overflows": overflow}
 

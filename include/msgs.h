@@ -210,6 +210,24 @@ int msgs_render(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
 int msgs_render_backward(msgs_context* ctx, const msgs_frame* frame, const float* dL_drgb,
                          const msgs_grads* out, void* stream);
 
+/* Backward of several renders of one scene (a multi-scale training step, Sec. 4.1,
+ * paragraph on multi-scale training and selective rendering:
+ * the loss is a sum over views, so the parameter gradients are the sum of the
+ * per-view adjoints).  Equivalent to msgs_render_backward on frames[0] with
+ * out->accumulate as given, then on frames[1..nviews-1] with accumulate = 1,
+ * with bit-identical results: the views' contributions are added in view
+ * order in fp32.  The per-view compositing adjoints run one after another;
+ * the chain rule then reads each Gaussian's parameters and writes its
+ * gradients once for up to eight views (more views take further passes).
+ *   frames   host array of nviews frames of the same scene and context
+ *   dL_drgb  host array of nviews device pointers, [H_d][W_d][3] fp32 each
+ *   nviews   >= 1 (else MSGS_E_INVALID)
+ * Temporary device memory: 48 bytes per Gaussian per view plus 52 bytes per
+ * tile instance of the largest frame. */
+int msgs_render_backward_views(msgs_context* ctx, const msgs_frame* const* frames,
+                               const float* const* dL_drgb, int nviews, const msgs_grads* out,
+                               void* stream);
+
 /* Planar Gaussians produced by the library (caller-owned device arrays with
  * room for `cap` Gaussians, same layout as msgs_scene_desc with n = cap). */
 typedef struct {

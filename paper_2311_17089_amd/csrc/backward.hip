@@ -51,7 +51,7 @@ __device__ __forceinline__ float wave_sum_to_63(float v) {
 // reduction: four DPP exchange stages inside each 16-lane row, each halving
 // the values a lane keeps (lane ^ 8 by row rotation, then the half-row mirror,
 // then lane ^ 2 and lane ^ 1), so that every lane ends with the row sum of one
-// of the nine values; two cross-row exchanges complete the wave sums.  Lane L
+// of the nine values; two cross-row swaps complete the wave sums.  Lane L
 // (L < 16) then holds the total of value kSlotQ(L) (15 = none).
 constexpr unsigned long long kSlotTable = 0xfff8f765ff43f210ull;
 __device__ __forceinline__ int slot_q(int lane) { return (int)((kSlotTable >> (4 * lane)) & 0xF); }
@@ -88,9 +88,14 @@ __device__ __forceinline__ float wave_reduce9(const float (&v)[9], int lane) {
   const float keep = b0 ? d[1] : d[0];
   const float send = b0 ? d[0] : d[1];
   float e = keep + MSGS_DPP(send, 0xB1);  // quad_perm [1,0,3,2]
-  e += __shfl_xor(e, 16, 64);
-  e += __shfl_xor(e, 32, 64);
-  return e;
+  // rows 0+1 and 2+3, then halves: lane-pair swaps that stay in the VALU
+  // (the sums are those of lane ^ 16 and lane ^ 32, in the same order)
+  const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(e), __float_as_uint(e), false,
+                                                    false);
+  e = __uint_as_float(r16[0]) + __uint_as_float(r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(e), __float_as_uint(e), false,
+                                                    false);
+  return __uint_as_float(r32[0]) + __uint_as_float(r32[1]);
 }
 #undef MSGS_DPP
 
@@ -348,60 +353,25 @@ __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
   }
 }
 
-// Chain rule per Gaussian (SH degree D as a template parameter so that the
-// coefficient loads are issued together).  ACC: add into the gradient planes
-// instead of writing them; Gaussians that do not contribute are then not
-// touched at all.
-template <bool ACC>
-__device__ __forceinline__ void put(float* p, int64_t i, float x) {
-  if (ACC)
-    p[i] += x;
-  else
-    p[i] = x;
-}
-
-template <int D, bool ACC>
-__global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, const uint32_t* count,
-                                                  const float* gsum, float* g_means,
-                                                  float* g_scales, float* g_quats,
-                                                  float* g_opacity, float* g_sh) {
-  const int64_t n = s.n;
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (k >= n) return;
+// Chain rule of one Gaussian under one view, from its nine summed partials G
+// (dL/du, dL/dA, dL/dopacity, dL/dcolour) back to the parameters.  Each
+// result x of output slot i goes to emit(i, x); the slots are means 0..2,
+// scales 3..5, quats 6..9, opacity 10 and the SH coefficients (j*3 + c) from
+// 11.  geo_shape and geo_view of this view must have filled g.
+template <int D, class Emit>
+__device__ __forceinline__ void chain_view(const ViewParams& v, const Geo& g, const float* G,
+                                           float mu0, float mu1, float mu2, const float* f,
+                                           Emit&& emit) {
   constexpr int K = (D + 1) * (D + 1);
-  Geo g;
-  bool live = count[k] > 0 && project_geo(s, v, k, g);
-  if (!live) {
-    if (ACC) return;
-    for (int i = 0; i < 3; ++i) g_means[i * n + k] = 0.0f;
-    for (int i = 0; i < 3; ++i) g_scales[i * n + k] = 0.0f;
-    for (int i = 0; i < 4; ++i) g_quats[i * n + k] = 0.0f;
-    g_opacity[k] = 0.0f;
-#pragma unroll
-    for (int j = 0; j < K * 3; ++j) g_sh[(int64_t)j * n + k] = 0.0f;
-    return;
-  }
-  float G[kNP];
-  {
-    const float4* Gp = (const float4*)gsum + k * 3;
-    const float4 a = Gp[0], b = Gp[1], c = Gp[2];
-    G[0] = a.x; G[1] = a.y; G[2] = a.z; G[3] = a.w;
-    G[4] = b.x; G[5] = b.y; G[6] = b.z; G[7] = b.w;
-    G[8] = c.x;
-  }
   const float gux = G[0], guy = G[1], gA11 = G[2], gA12 = G[3], gA22 = G[4];
-  put<ACC>(g_opacity, k, G[5]);
+  emit(10, G[5]);
   // ---- colour -> SH coefficients and view direction
-  const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
   float dv0 = mu0 - v.C[0], dv1 = mu1 - v.C[1], dv2 = mu2 - v.C[2];
   const float dn = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
   const float x = dv0 / dn, y = dv1 / dn, z = dv2 / dn;
   float Y[16], Yx[16], Yy[16], Yz[16];
   sh_eval(D, x, y, z, Y);
   sh_grad(D, x, y, z, Yx, Yy, Yz);
-  float f[K * 3];
-#pragma unroll
-  for (int j = 0; j < K * 3; ++j) f[j] = s.sh[(int64_t)j * n + k];
   float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -411,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
     const float gc = acc < 0.0f ? 0.0f : G[6 + c];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      put<ACC>(g_sh, (int64_t)(j * 3 + c) * n + k, Y[j] * gc);
+      emit(11 + j * 3 + c, Y[j] * gc);
       gdx += gc * f[j * 3 + c] * Yx[j];
       gdy += gc * f[j * 3 + c] * Yy[j];
       gdz += gc * f[j * 3 + c] * Yz[j];
@@ -467,9 +437,9 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
   gm0 += R[0] * gp0 + R[3] * gp1 + R[6] * gp2;
   gm1 += R[1] * gp0 + R[4] * gp1 + R[7] * gp2;
   gm2 += R[2] * gp0 + R[5] * gp1 + R[8] * gp2;
-  put<ACC>(g_means, k, gm0);
-  put<ACC>(g_means, n + k, gm1);
-  put<ACC>(g_means, 2 * n + k, gm2);
+  emit(0, gm0);
+  emit(1, gm1);
+  emit(2, gm2);
   // ---- Sigma = M M^T, M = Q diag(s)
   float M[3][3];
   for (int i = 0; i < 3; ++i)
@@ -479,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
     for (int j = 0; j < 3; ++j) gM[i][j] = Gs[i][0] * M[0][j] + Gs[i][1] * M[1][j] + Gs[i][2] * M[2][j];
   float gQ[9];
   for (int j = 0; j < 3; ++j) {
-    put<ACC>(g_scales, j * n + k, gM[0][j] * g.Q[j] + gM[1][j] * g.Q[3 + j] + gM[2][j] * g.Q[6 + j]);
+    emit(3 + j, gM[0][j] * g.Q[j] + gM[1][j] * g.Q[3 + j] + gM[2][j] * g.Q[6 + j]);
     for (int i = 0; i < 3; ++i) gQ[i * 3 + j] = gM[i][j] * g.sc[j];
   }
   // ---- Q(q_hat) -> q_hat -> raw q
@@ -494,10 +464,111 @@ __global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, con
                    4.0f * qz * gQ[4] + 2.0f * qy * gQ[5] + 2.0f * qx * gQ[6] + 2.0f * qy * gQ[7];
   const float dq = w * gw + qx * gx + qy * gy + qz * gz;
   const float il = 1.0f / g.qlen;
-  put<ACC>(g_quats, k, (gw - w * dq) * il);
-  put<ACC>(g_quats, n + k, (gx - qx * dq) * il);
-  put<ACC>(g_quats, 2 * n + k, (gy - qy * dq) * il);
-  put<ACC>(g_quats, 3 * n + k, (gz - qz * dq) * il);
+  emit(6, (gw - w * dq) * il);
+  emit(7, (gx - qx * dq) * il);
+  emit(8, (gy - qy * dq) * il);
+  emit(9, (gz - qz * dq) * il);
+}
+
+struct GradPlanes {
+  float* means;
+  float* scales;
+  float* quats;
+  float* opacity;
+  float* sh;
+};
+
+__device__ __forceinline__ void load9(const float* gsum, int64_t k, float* G) {
+  const float4* Gp = (const float4*)gsum + k * 3;
+  const float4 a = Gp[0], b = Gp[1], c = Gp[2];
+  G[0] = a.x; G[1] = a.y; G[2] = a.z; G[3] = a.w;
+  G[4] = b.x; G[5] = b.y; G[6] = b.z; G[7] = b.w;
+  G[8] = c.x;
+}
+
+// Address of output slot i (see chain_view) of Gaussian k in the planar arrays.
+__device__ __forceinline__ float* slot_ptr(const GradPlanes& p, int64_t n, int64_t k, int i) {
+  if (i < 3) return p.means + i * n + k;
+  if (i < 6) return p.scales + (i - 3) * n + k;
+  if (i < 10) return p.quats + (i - 6) * n + k;
+  if (i == 10) return p.opacity + k;
+  return p.sh + (int64_t)(i - 11) * n + k;
+}
+
+template <int D>
+__device__ __forceinline__ void load_sh(const SceneView& s, int64_t k, float* f) {
+  constexpr int K = (D + 1) * (D + 1);
+#pragma unroll
+  for (int j = 0; j < K * 3; ++j) f[j] = s.sh[(int64_t)j * s.n + k];
+}
+
+// One view (SH degree D as a template parameter so that the coefficient loads
+// are issued together).  ACC: add into the gradient planes instead of writing
+// them; Gaussians that do not contribute are then not touched at all.
+template <int D, bool ACC>
+__global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, const uint32_t* count,
+                                                  const float* gsum, GradPlanes p) {
+  const int64_t n = s.n;
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  constexpr int K = (D + 1) * (D + 1);
+  Geo g;
+  bool live = count[k] > 0 && project_geo(s, v, k, g);
+  if (!live) {
+    if (ACC) return;
+#pragma unroll
+    for (int i = 0; i < 11 + K * 3; ++i) *slot_ptr(p, n, k, i) = 0.0f;
+    return;
+  }
+  float G[kNP], f[K * 3];
+  load9(gsum, k, G);
+  load_sh<D>(s, k, f);
+  const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
+  chain_view<D>(v, g, G, mu0, mu1, mu2, f, [&](int i, float x) {
+    float* q = slot_ptr(p, n, k, i);
+    if (ACC)
+      *q += x;
+    else
+      *q = x;
+  });
+}
+
+// Several views in one pass: the parameters of a Gaussian are read and its
+// gradients written once, the views' contributions added in view order (the
+// same fp32 additions, in the same order, as one k_chain per view with the
+// first writing and the rest adding).
+template <int D, bool ACC>
+__global__ __launch_bounds__(kBlock) void k_chain_views(SceneView s, ChainViews cv, GradPlanes p) {
+  const int64_t n = s.n;
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  constexpr int K = (D + 1) * (D + 1);
+  constexpr int NO = 11 + K * 3;
+  uint32_t live = 0;
+  for (int i = 0; i < cv.nv; ++i) live |= (cv.w[i].count[k] > 0 ? 1u : 0u) << i;
+  if (!live) {
+    if (ACC) return;
+#pragma unroll
+    for (int i = 0; i < NO; ++i) *slot_ptr(p, n, k, i) = 0.0f;
+    return;
+  }
+  Geo g;
+  geo_shape(s, k, g);
+  float f[K * 3];
+  load_sh<D>(s, k, f);
+  const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
+  float o[NO];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) o[i] = ACC ? *slot_ptr(p, n, k, i) : 0.0f;
+  for (int i = 0; i < cv.nv; ++i) {
+    if (!((live >> i) & 1u)) continue;
+    if (!geo_view(cv.w[i].v, mu0, mu1, mu2, g)) continue;
+    float G[kNP];
+    load9(cv.w[i].gsum, k, G);
+    chain_view<D>(cv.w[i].v, g, G, mu0, mu1, mu2, f, [&](int j, float x) { o[j] = o[j] + x; });
+  }
+#pragma unroll
+  for (int i = 0; i < NO; ++i) *slot_ptr(p, n, k, i) = o[i];
 }
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -516,32 +587,59 @@ void launch_backward_blend(const BwdArgs& a, hipStream_t st) {
   }
 }
 
+static GradPlanes planes_of(const BwdArgs& a) {
+  return GradPlanes{a.g_means, a.g_scales, a.g_quats, a.g_opacity, a.g_sh};
+}
+
 template <int D>
 static void launch_chain_d(const BwdArgs& a, dim3 g, dim3 b, hipStream_t st) {
   if (a.accumulate)
-    hipLaunchKernelGGL((k_chain<D, true>), g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means,
-                       a.g_scales, a.g_quats, a.g_opacity, a.g_sh);
+    hipLaunchKernelGGL((k_chain<D, true>), g, b, 0, st, a.s, a.v, a.count, a.gsum, planes_of(a));
   else
-    hipLaunchKernelGGL((k_chain<D, false>), g, b, 0, st, a.s, a.v, a.count, a.gsum, a.g_means,
-                       a.g_scales, a.g_quats, a.g_opacity, a.g_sh);
+    hipLaunchKernelGGL((k_chain<D, false>), g, b, 0, st, a.s, a.v, a.count, a.gsum, planes_of(a));
+}
+
+void launch_backward_segsum(const BwdArgs& a, hipStream_t st) {
+  if (a.s.n == 0 || a.n_vis == 0) return;
+  hipLaunchKernelGGL(k_seg_small, dim3(grid_for(a.n_vis)), dim3(kBlock), 0, st, a.order, a.n_vis,
+                     a.d_nvis, a.count, a.emit_base, a.partial, a.wmask, a.gsum, a.big, a.nbig);
+  hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, a.partial,
+                     a.wmask, a.gsum, a.big, a.nbig);
 }
 
 void launch_backward_chain(const BwdArgs& a, hipStream_t st) {
   const int64_t n = a.s.n;
   if (n == 0) return;
-  if (a.n_vis > 0) {
-    hipLaunchKernelGGL(k_seg_small, dim3(grid_for(a.n_vis)), dim3(kBlock), 0, st, a.order, a.n_vis,
-                       a.d_nvis,
-                       a.count, a.emit_base, a.partial, a.wmask, a.gsum, a.big, a.nbig);
-    hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, a.partial,
-                       a.wmask, a.gsum, a.big, a.nbig);
-  }
+  launch_backward_segsum(a, st);
   const dim3 g(grid_for(n)), b(kBlock);
   switch (a.s.sh_degree) {
     case 0: launch_chain_d<0>(a, g, b, st); break;
     case 1: launch_chain_d<1>(a, g, b, st); break;
     case 2: launch_chain_d<2>(a, g, b, st); break;
     default: launch_chain_d<3>(a, g, b, st); break;
+  }
+}
+
+template <int D>
+static void launch_views_d(const SceneView& s, const ChainViews& cv, const GradPlanes& p, bool acc,
+                           hipStream_t st) {
+  const dim3 g(grid_for(s.n)), b(kBlock);
+  if (acc)
+    hipLaunchKernelGGL((k_chain_views<D, true>), g, b, 0, st, s, cv, p);
+  else
+    hipLaunchKernelGGL((k_chain_views<D, false>), g, b, 0, st, s, cv, p);
+}
+
+void launch_chain_views(const SceneView& s, const ChainViews& cv, float* g_means, float* g_scales,
+                        float* g_quats, float* g_opacity, float* g_sh, int accumulate,
+                        hipStream_t st) {
+  if (s.n == 0 || cv.nv <= 0) return;
+  const GradPlanes p{g_means, g_scales, g_quats, g_opacity, g_sh};
+  switch (s.sh_degree) {
+    case 0: launch_views_d<0>(s, cv, p, accumulate != 0, st); break;
+    case 1: launch_views_d<1>(s, cv, p, accumulate != 0, st); break;
+    case 2: launch_views_d<2>(s, cv, p, accumulate != 0, st); break;
+    default: launch_views_d<3>(s, cv, p, accumulate != 0, st); break;
   }
 }
 

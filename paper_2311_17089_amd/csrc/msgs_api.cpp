@@ -615,6 +615,88 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   return rc;
 }
 
+int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
+                               const float* const* dL_drgb, int nviews, const msgs_grads* out,
+                               void* stream) {
+  if (!c || !frames || !dL_drgb || !out) return fail(MSGS_E_INVALID, "null argument");
+  if (nviews < 1) return fail(MSGS_E_INVALID, "nviews must be at least 1");
+  const msgs_scene* scene = nullptr;
+  int64_t max_inst = 0;
+  for (int i = 0; i < nviews; ++i) {
+    const msgs_frame* f = frames[i];
+    if (!f || !dL_drgb[i]) return fail(MSGS_E_INVALID, "null frame or dL_drgb");
+    if (f->ctx != c) return fail(MSGS_E_INVALID, "frame belongs to another context");
+    if (i == 0) scene = f->scene;
+    if (f->scene != scene) return fail(MSGS_E_INVALID, "frames of different scenes");
+    max_inst = std::max<int64_t>(max_inst, f->n_inst);
+  }
+  const int64_t n = frames[0]->n;
+  if (n > 0 && (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh))
+    return fail(MSGS_E_INVALID, "null gradient array");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  float* partial = nullptr;
+  uint32_t* wmask = nullptr;
+  float* gsum = nullptr;
+  uint32_t* big = nullptr;
+  uint32_t* nbig = nullptr;
+  Carve tmp;
+  tmp.add((void**)&partial, (size_t)48 * (size_t)max_inst);
+  tmp.add((void**)&wmask, (size_t)4 * (size_t)((max_inst + 31) / 32));
+  tmp.add((void**)&gsum, (size_t)48 * (size_t)n * (size_t)nviews);
+  tmp.add((void**)&big, (size_t)4 * (size_t)n);
+  tmp.add((void**)&nbig, 4);
+  int rc = tmp.alloc(c, st);
+  if (rc != MSGS_OK) return rc;
+  // per view: adjoint compositing and the per-Gaussian partial sums
+  for (int i = 0; i < nviews; ++i) {
+    const msgs_frame* f = frames[i];
+    BwdArgs a{};
+    a.s = f->scene->view;
+    a.v = f->v;
+    a.ranges = f->ranges;
+    a.tvals = f->tvals;
+    a.rec = f->rec;
+    a.rect = f->rect;
+    a.emit_base = f->emit_base;
+    a.count = f->count;
+    a.order = f->order;
+    a.n_vis = f->n_vis;
+    a.d_nvis = (const uint32_t*)&f->ctr[2];
+    a.T_final = f->T_final;
+    a.n_last = f->n_last;
+    a.dL_drgb = dL_drgb[i];
+    a.n_inst = f->n_inst;
+    a.partial = partial;
+    a.wmask = wmask;
+    a.gsum = gsum + (size_t)12 * (size_t)n * (size_t)i;
+    a.big = big;
+    a.nbig = nbig;
+    launch_fill_u32(nbig, 1, 0u, st);
+    launch_backward_zero(a, st);
+    launch_backward_blend(a, st);
+    launch_backward_segsum(a, st);
+  }
+  // chain rule, kChainViews views per pass; later passes add
+  for (int i0 = 0; i0 < nviews; i0 += kChainViews) {
+    ChainViews cv{};
+    cv.nv = std::min(kChainViews, nviews - i0);
+    for (int j = 0; j < cv.nv; ++j) {
+      const msgs_frame* f = frames[i0 + j];
+      cv.w[j].v = f->v;
+      cv.w[j].count = f->count;
+      cv.w[j].gsum = gsum + (size_t)12 * (size_t)n * (size_t)(i0 + j);
+    }
+    launch_chain_views(frames[0]->scene->view, cv, out->means, out->scales, out->quats,
+                       out->opacity, out->sh, (out->accumulate || i0 > 0) ? 1 : 0, st);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) rc = hip_fail(e, "backward launch");
+  c->cache.free(c, tmp.base, st);
+  return rc;
+}
+
 int msgs_frame_release(msgs_frame* f) {
   if (!f) return fail(MSGS_E_INVALID, "null frame");
   (void)hipSetDevice(f->ctx->device);

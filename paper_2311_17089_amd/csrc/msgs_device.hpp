@@ -204,8 +204,9 @@ struct Geo {
   float Tm[6];    // J R rows (0: 0..2, 1: 3..5)
 };
 
-__device__ __forceinline__ bool project_geo(const SceneView& s, const ViewParams& v, int64_t k,
-                                            Geo& g) {
+// The part of the geometry that does not depend on the view: normalised
+// quaternion, its rotation, scales and the 3D covariance Sigma = M M^T.
+__device__ __forceinline__ void geo_shape(const SceneView& s, int64_t k, Geo& g) {
   const int64_t n = s.n;
   float qw = s.quats[k], qx = s.quats[n + k], qy = s.quats[2 * n + k], qz = s.quats[3 * n + k];
   float nrm2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
@@ -234,7 +235,14 @@ __device__ __forceinline__ bool project_geo(const SceneView& s, const ViewParams
     }
   g.Sg[0] = S[0][0]; g.Sg[1] = S[0][1]; g.Sg[2] = S[0][2];
   g.Sg[3] = S[1][1]; g.Sg[4] = S[1][2]; g.Sg[5] = S[2][2];
-  float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
+}
+
+// The view-dependent part, given geo_shape's fields and the mean mu.
+__device__ __forceinline__ bool geo_view(const ViewParams& v, float mu0, float mu1, float mu2,
+                                         Geo& g) {
+  const float S[3][3] = {{g.Sg[0], g.Sg[1], g.Sg[2]},
+                         {g.Sg[1], g.Sg[3], g.Sg[4]},
+                         {g.Sg[2], g.Sg[4], g.Sg[5]}};
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     g.p[i] = ((v.R[i * 3 + 0] * mu0 + v.R[i * 3 + 1] * mu1) + v.R[i * 3 + 2] * mu2) + v.t[i];
@@ -264,6 +272,13 @@ __device__ __forceinline__ bool project_geo(const SceneView& s, const ViewParams
   g.ux = (v.fx * px) / pz + v.cx;
   g.uy = (v.fy * py) / pz + v.cy;
   return true;
+}
+
+__device__ __forceinline__ bool project_geo(const SceneView& s, const ViewParams& v, int64_t k,
+                                            Geo& g) {
+  const int64_t n = s.n;
+  geo_shape(s, k, g);
+  return geo_view(v, s.means[k], s.means[n + k], s.means[2 * n + k], g);
 }
 
 // Pixel coverage (Sec. 4.1): the shorter of the centre chords along screen x and

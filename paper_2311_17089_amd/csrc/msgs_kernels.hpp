@@ -74,7 +74,25 @@ struct BwdArgs {
 };
 void launch_backward_zero(const BwdArgs& a, hipStream_t st);
 void launch_backward_blend(const BwdArgs& a, hipStream_t st);
-void launch_backward_chain(const BwdArgs& a, hipStream_t st);
+void launch_backward_chain(const BwdArgs& a, hipStream_t st);   // segment sums + chain rule
+void launch_backward_segsum(const BwdArgs& a, hipStream_t st);  // segment sums into a.gsum
+
+// Chain rule over several views in one pass (up to kChainViews per launch):
+// view i's frame-level inputs are its ViewParams, its per-Gaussian tile counts
+// and its per-Gaussian partial sums.
+constexpr int kChainViews = 8;
+struct ChainView {
+  ViewParams v;
+  const uint32_t* count;
+  const float* gsum;
+};
+struct ChainViews {
+  ChainView w[kChainViews];
+  int nv;
+};
+void launch_chain_views(const SceneView& s, const ChainViews& cv, float* g_means, float* g_scales,
+                        float* g_quats, float* g_opacity, float* g_sh, int accumulate,
+                        hipStream_t st);
 
 // aggregation (Alg. 1): voxel key of a Gaussian that is not chosen
 constexpr uint32_t kAggNone = 0xFFFFFFu;

@@ -87,6 +87,8 @@ EXPORTS = {
     "msgs_render": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p], C.c_int),
     "msgs_render_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_render_backward_views": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                    C.c_void_p], C.c_int),
     "msgs_frame_release": ([C.c_void_p], C.c_int),
     "msgs_frame_stats": ([C.c_void_p, C.c_void_p], C.c_int),
     "msgs_frame_get_selection": ([C.c_void_p, C.c_void_p], C.c_int),
@@ -296,14 +298,7 @@ def render(ctx: Context, scene: DeviceScene, cam, downscale=1, selective=True,
     return out
 
 
-def render_backward(ctx: Context, frame: Frame, dL_drgb: torch.Tensor, stream=None,
-                    grads: Optional[dict] = None, accumulate: bool = False) -> dict:
-    """Adjoint of `render` for the frame's decisions; returns gradient tensors
-    w.r.t. means, scales (linear), quats (raw), opacity and sh.  With `grads`
-    (tensors shaped like the scene's) they receive the result; with
-    accumulate=True it is added to them."""
-    sc = frame.scene
-    assert dL_drgb.is_contiguous() and dL_drgb.dtype == torch.float32
+def _grad_planes(sc, grads, accumulate):
     names = ("means", "scales", "quats", "opacity", "sh")
     if grads is None:
         if accumulate:
@@ -315,9 +310,39 @@ def render_backward(ctx: Context, frame: Frame, dL_drgb: torch.Tensor, stream=No
             t = g[k]
             assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
             assert t.shape == sc.t[k].shape, k
-    gs = Grads(*[g[k].data_ptr() for k in names], 1 if accumulate else 0)
+    return g, Grads(*[g[k].data_ptr() for k in names], 1 if accumulate else 0)
+
+
+def render_backward(ctx: Context, frame: Frame, dL_drgb: torch.Tensor, stream=None,
+                    grads: Optional[dict] = None, accumulate: bool = False) -> dict:
+    """Adjoint of `render` for the frame's decisions; returns gradient tensors
+    w.r.t. means, scales (linear), quats (raw), opacity and sh.  With `grads`
+    (tensors shaped like the scene's) they receive the result; with
+    accumulate=True it is added to them."""
+    assert dL_drgb.is_contiguous() and dL_drgb.dtype == torch.float32
+    g, gs = _grad_planes(frame.scene, grads, accumulate)
     check(lib().msgs_render_backward(ctx.h, frame.h, C.c_void_p(dL_drgb.data_ptr()), C.byref(gs),
                                      C.c_void_p(_stream(stream))))
+    return g
+
+
+def render_backward_views(ctx: Context, frames, dL_drgbs, stream=None,
+                          grads: Optional[dict] = None, accumulate: bool = False) -> dict:
+    """Backward of several renders of one scene at once: the sum over views of
+    `render_backward`, bit-identical to calling it per view with the first
+    call writing (or adding, with accumulate=True) and the rest adding."""
+    frames, dL_drgbs = list(frames), list(dL_drgbs)
+    if len(frames) != len(dL_drgbs):
+        raise ValueError("one dL_drgb per frame")
+    for d in dL_drgbs:
+        assert d.is_contiguous() and d.dtype == torch.float32
+    if not frames:
+        raise ValueError("no frames")
+    g, gs = _grad_planes(frames[0].scene, grads, accumulate)
+    fa = (C.c_void_p * len(frames))(*[f.h for f in frames])
+    da = (C.c_void_p * len(frames))(*[d.data_ptr() for d in dL_drgbs])
+    check(lib().msgs_render_backward_views(ctx.h, fa, da, len(frames), C.byref(gs),
+                                           C.c_void_p(_stream(stream))))
     return g
 
 
