@@ -9,7 +9,8 @@
 //  k_compact   order-preserving compaction of drawable Gaussians into
 //              (depth key, index) pairs (wave ballot + block prefix).
 //  k_emit      one instance (tile, Gaussian) per tile of each rectangle,
-//              row-major, Gaussians in depth order (load-balanced per wave).
+//              row-major, Gaussians in depth order (each wave writes its
+//              Gaussians' contiguous stretch of the list, 64 at a time).
 //  k_ranges    half-open range of every tile in the tile-sorted list.
 //  k_blend     one 256-thread workgroup per 16x16 tile whose four wave64s
 //              work independently on their 8x8 quadrants: per 64-instance chunk
@@ -174,19 +175,22 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* count, const
   }
 }
 
-constexpr uint32_t kEmitSmall = 16;
-
 // One (tile, Gaussian) instance per tile of every drawable Gaussian, in depth
-// order, tiles of a rectangle row-major.  A Gaussian with at most kEmitSmall
-// tiles is written by its own thread; larger ones are written by the whole
-// wave, 64 consecutive instances at a time.
+// order, tiles of a rectangle row-major.  The 64 Gaussians of a wave own one
+// contiguous stretch of the list (their exclusive-scan offsets), which the
+// wave writes 64 consecutive instances at a time: lane i takes position
+// p0 + i, finds its Gaussian by a binary search over the wave's offsets in LDS
+// (the last one not above p) and its tile from the rectangle.  Every store
+// instruction covers 256 contiguous bytes.
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* order, const uint32_t* off,
                                                  const uint32_t* d_nvis, const uint32_t* count,
                                                  const uint2* rect, int Tx, uint32_t* tkeys,
                                                  uint32_t* tvals, uint32_t* emit_base,
                                                  uint32_t cap) {
+  __shared__ uint32_t sb[kBlock / 64][64], sk[kBlock / 64][64];
+  __shared__ uint2 sr[kBlock / 64][64];
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool valid = j < (int64_t)*d_nvis;
   uint32_t k = 0, base = 0, c = 0;
   uint2 r = make_uint2(0u, 0u);
@@ -197,35 +201,31 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* order, const ui
     r = rect[k];
     emit_base[k] = base;
   }
-  const bool big = valid && c > kEmitSmall;
-  if (valid && !big) {
-    const int xl = r.x & 0xffff, xh = r.x >> 16, yl = r.y & 0xffff, yh = r.y >> 16;
-    uint32_t i = base;
-    for (int ty = yl; ty <= yh; ++ty) {
-      const uint32_t row = (uint32_t)ty * (uint32_t)Tx;
-      for (int tx = xl; tx <= xh; ++tx) {
-        if (i < cap) {
-          tkeys[i] = row + (uint32_t)tx;
-          tvals[i] = k;
-        }
-        ++i;
-      }
-    }
-  }
-  unsigned long long m = __ballot(big);
-  while (m) {
-    const int src = __ffsll((long long)m) - 1;
-    m &= m - 1;
-    const uint32_t bk = __shfl(k, src, 64), bb = __shfl(base, src, 64), bc = __shfl(c, src, 64);
-    const uint32_t rx = __shfl(r.x, src, 64), ry = __shfl(r.y, src, 64);
-    const uint32_t xl = rx & 0xffff, xh = rx >> 16, yl = ry & 0xffff;
-    const uint32_t nx = xh - xl + 1;
-    for (uint32_t li = lane; li < bc; li += 64) {
+  const unsigned long long vm = __ballot(valid);
+  if (vm == 0ull) return;  // whole wave past the drawable list (valid lanes are a prefix)
+  const int nv = 64 - __clzll((long long)vm);  // valid lanes: 0 .. nv-1
+  sb[wave][lane] = valid ? base : 0xFFFFFFFFu;  // above every position
+  sk[wave][lane] = k;
+  sr[wave][lane] = r;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t b0 = __shfl(base, 0, 64);
+  const uint32_t b1 = __shfl(base + c, nv - 1, 64);
+  const uint32_t* wb = sb[wave];
+  for (uint32_t p0 = b0; p0 < b1; p0 += 64u) {
+    const uint32_t p = p0 + (uint32_t)lane;
+    if (p < b1 && p < cap) {
+      int o = 0;  // wb[o] <= p throughout; ends at the last such index
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) o += wb[o + step] <= p ? step : 0;
+      const uint2 ro = sr[wave][o];
+      const uint32_t li = p - wb[o];
+      const uint32_t xl = ro.x & 0xffffu, xh = ro.x >> 16, yl = ro.y & 0xffffu;
+      const uint32_t nx = xh - xl + 1u;
       const uint32_t dy = li / nx, dx = li - dy * nx;
-      if (bb + li < cap) {
-        tkeys[bb + li] = (yl + dy) * (uint32_t)Tx + xl + dx;
-        tvals[bb + li] = bk;
-      }
+      tkeys[p] = (yl + dy) * (uint32_t)Tx + xl + dx;
+      tvals[p] = sk[wave][o];
     }
   }
 }

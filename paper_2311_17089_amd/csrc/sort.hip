@@ -120,6 +120,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_lb(const uint32_t* in, const ui
   const int64_t t = s_tile;
   const int64_t n = d_n ? (int64_t)*d_n : nmax;
   const int64_t base = t * kScanTile;
+  // tiles past the last input element only zero their outputs: they publish
+  // no status (no live tile looks back that far) and take no look-back
+  const int64_t tlast = n > 0 ? (n - 1) / kScanTile : 0;
+  if (t > tlast) {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const int64_t idx = base + i * kBlock + threadIdx.x;
+      if (idx < nmax) out[idx] = 0u;
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int e = i * kBlock + threadIdx.x;
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_lb(const uint32_t* in, const ui
       st_status(status + t, kFlagP | (ex + tot));
       s_base = ex;
     }
-    if (t == (int64_t)gridDim.x - 1 && total) *total = s_base + tot;
+    if (t == tlast && total) *total = s_base + tot;
   }
   __syncthreads();
   run += (uint32_t)s_base;
@@ -236,6 +247,9 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   const int64_t t = s_tile;
   const int64_t n = d_n ? (int64_t)*d_n : nmax;
   const int64_t tbase = t * TILE;
+  // a tile past the input has nothing to move, and no tile that has items
+  // looks back at it (tickets are taken in order)
+  if (tbase >= n) return;
   const int64_t wbase = tbase + (int64_t)wave * (64 * ITEMS);
   const uint32_t mask = (1u << nbits) - 1u;
   // number of valid items of this wave's slice (32-bit offsets from here on)
