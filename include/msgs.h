@@ -322,6 +322,14 @@ int msgs_server_destroy(msgs_server* s);
  * floats.  For verification of the numerics contract. */
 int msgs_debug_exp(const float* x, float* y, int64_t n, void* stream);
 int msgs_debug_log(const float* x, float* y, int64_t n, void* stream);
+/* The library's stable LSD radix sort of (u32 key, u32 value) pairs by key
+ * bits [begin_bit, end_bit), in place on device arrays of nmax entries.  Sorts
+ * the first *d_n entries when d_n (device u32, at most nmax) is non-null, else
+ * all nmax; entries past the count are left unspecified.  The sort that orders
+ * Gaussians by depth and tile instances by tile (Sec. 3.1); for verification.
+ * Temporary memory comes from the context.  Synchronises `stream`. */
+int msgs_debug_sort_pairs(msgs_context* ctx, uint32_t* keys, uint32_t* vals, const uint32_t* d_n,
+                          int64_t nmax, int begin_bit, int end_bit, void* stream);
 
 #ifdef __cplusplus
 }

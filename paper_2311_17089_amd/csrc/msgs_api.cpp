@@ -838,4 +838,33 @@ int msgs_debug_log(const float* x, float* y, int64_t n, void* stream) {
   return e == hipSuccess ? MSGS_OK : hip_fail(e, "debug log");
 }
 
+int msgs_debug_sort_pairs(msgs_context* c, uint32_t* keys, uint32_t* vals, const uint32_t* d_n,
+                          int64_t nmax, int begin_bit, int end_bit, void* stream) {
+  if (!c) return fail(MSGS_E_INVALID, "null context");
+  if (nmax < 0 || nmax > 0xFFFFFFFFll) return fail(MSGS_E_INVALID, "nmax out of range");
+  if (nmax > 0 && (!keys || !vals)) return fail(MSGS_E_INVALID, "null array");
+  if (begin_bit < 0 || end_bit > 32 || begin_bit > end_bit)
+    return fail(MSGS_E_INVALID, "bit range out of [0, 32]");
+  if (nmax == 0 || begin_bit == end_bit) return MSGS_OK;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t *ka = nullptr, *va = nullptr;
+  void* stmp = nullptr;
+  Carve tmp;
+  tmp.add(&ka, (size_t)nmax * 4);
+  tmp.add(&va, (size_t)nmax * 4);
+  tmp.add(&stmp, radix_tmp_bytes(nmax, radix_passes(begin_bit, end_bit)));
+  int rc = tmp.alloc(c, st);
+  if (rc != MSGS_OK) return rc;
+  if (radix_sort_pairs(keys, vals, ka, va, d_n, nmax, begin_bit, end_bit, stmp, st)) {
+    (void)hipMemcpyAsync(keys, ka, (size_t)nmax * 4, hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(vals, va, (size_t)nmax * 4, hipMemcpyDeviceToDevice, st);
+  }
+  c->cache.free(c, tmp.base, st);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? MSGS_OK : hip_fail(e, "debug sort");
+}
+
 }  // extern "C"

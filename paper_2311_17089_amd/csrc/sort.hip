@@ -223,14 +223,54 @@ __global__ __launch_bounds__(kBlock) void k_os_hist(const uint32_t* keys, const 
   }
 }
 
+// Digit counts of one tile for the reduce-then-scan pass: counts[d * nblk + t]
+// (digit-major, so that one exclusive scan of the whole array gives every
+// (digit, tile) its global start).  Tiles past the input count nothing.
 template <int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* keys, const uint32_t* d_n,
+                                                     int64_t nmax, int shift, int nbits,
+                                                     uint32_t* counts, int64_t nblk) {
+  constexpr int TILE = kBlock * ITEMS;
+  __shared__ uint32_t h[kBlock / 64][kRadix];
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) h[w][threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = d_n ? (int64_t)*d_n : nmax;
+  const int64_t t = blockIdx.x;
+  const int64_t tbase = t * TILE;
+  const uint32_t mask = (1u << nbits) - 1u;
+  uint32_t k_[ITEMS];
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const int64_t idx = tbase + i * kBlock + threadIdx.x;
+    k_[i] = idx < n ? keys[idx] : 0u;
+  }
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i)
+    if (tbase + i * kBlock + threadIdx.x < n) atomicAdd(&h[wave][(k_[i] >> shift) & mask], 1u);
+  __syncthreads();
+  uint32_t c = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) c += h[w][threadIdx.x];
+  counts[(int64_t)threadIdx.x * nblk + t] = c;
+}
+
+// One pass of the sort.  RTS = false (onesweep): the tile's digit starts come
+// from the global histogram and a decoupled look-back over the tiles before
+// it.  RTS = true (reduce-then-scan): they are read from `starts`, the
+// exclusive scan of k_rs_count's digit-major counts, so no tile waits on
+// another (on a chip whose L2s are per XCD every look-back step is a trip to
+// memory, which long chains of tiles pay for one after another).
+template <int ITEMS, bool RTS>
 __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
                                                     const uint32_t* vals_in, uint32_t* keys_out,
                                                     uint32_t* vals_out, const uint32_t* d_n,
                                                     int64_t nmax, int shift, int nbits,
                                                     const uint32_t* hist,
                                                     unsigned long long* status,
-                                                    uint32_t* ticket) {
+                                                    uint32_t* ticket, const uint32_t* starts,
+                                                    int64_t nblk) {
   constexpr int TILE = kBlock * ITEMS;
   __shared__ uint32_t cnt[kBlock / 64][kRadix];
   __shared__ uint32_t ldig[kRadix];
@@ -240,11 +280,11 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   __shared__ uint8_t sdig[TILE];
   __shared__ int64_t s_tile;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
+  if (!RTS && threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
 #pragma unroll
   for (int w = 0; w < kBlock / 64; ++w) cnt[w][threadIdx.x] = 0;
   __syncthreads();
-  const int64_t t = s_tile;
+  const int64_t t = RTS ? (int64_t)blockIdx.x : s_tile;
   const int64_t n = d_n ? (int64_t)*d_n : nmax;
   const int64_t tbase = t * TILE;
   // a tile past the input has nothing to move, and no tile that has items
@@ -262,9 +302,13 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) k_[i] = i * 64 + lane < remw ? kin_w[i * 64 + lane] : 0u;
   // global start of every digit: exclusive scan of the digit totals
-  uint32_t htot;
-  const uint32_t hd = hist[threadIdx.x];
-  const uint32_t gs = block_excl_scan(hd, wtot, htot);
+  uint32_t htot, hd = 0, gs = 0;
+  if (!RTS) {
+    hd = hist[threadIdx.x];
+    gs = block_excl_scan(hd, wtot, htot);
+  } else {
+    gs = starts[(int64_t)threadIdx.x * nblk + t];
+  }
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const bool valid = i * 64 + lane < remw;
@@ -300,8 +344,8 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   }
   // a digit absent from the whole input has no status traffic at all: no
   // workgroup publishes or reads it (all see the same histogram)
-  const bool used = hd != 0u;
-  unsigned long long* st = status + t * kRadix + d;
+  const bool used = !RTS && hd != 0u;
+  unsigned long long* st = RTS ? nullptr : status + t * kRadix + d;
   if (used) st_status(st, (t == 0 ? kFlagP : kFlagA) | bt);
   uint32_t tot;
   ldig[d] = block_excl_scan(bt, wtot, tot);
@@ -321,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) v_[i] = i * 64 + lane < remw ? vin_w[i * 64 + lane] : 0u;
   unsigned long long excl = 0;
-  if (t > 0 && used) {
+  if (!RTS && t > 0 && used) {
     excl = look_back<4>(status + d, kRadix, t);
     st_status(st, kFlagP | (excl + bt));
   }
@@ -373,10 +417,16 @@ void scan_excl_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, co
                      out, total, status, ticket);
 }
 
+// Tiles from which a sort pass switches to reduce-then-scan.
+constexpr int64_t kRtsMinTiles = 512;
+
 size_t radix_tmp_bytes(int64_t nmax, int npass) {
   const int items = sort_items(nmax);
   const int64_t nblk = (nmax + kBlock * items - 1) / (kBlock * items);
-  return (size_t)npass * kRadix * 4 + (size_t)npass * (nblk > 0 ? nblk : 1) * kRadix * 8 + 64 * 4;
+  const int64_t nb = nblk > 0 ? nblk : 1;
+  const size_t onesweep = (size_t)npass * kRadix * 4 + (size_t)npass * nb * kRadix * 8 + 64 * 4;
+  const size_t rts = (size_t)2 * kRadix * nb * 4 + 256 + scan_tmp_bytes(kRadix * nb);
+  return std::max(onesweep, rts);
 }
 
 int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
@@ -387,6 +437,39 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
   const int items = sort_items(nmax);
   const int tile = kBlock * items;
   const int64_t nblk = (nmax + tile - 1) / tile;
+  const bool rts = nblk >= kRtsMinTiles;
+  uint32_t* kin = keys;
+  uint32_t* vin = vals;
+  uint32_t* kout = keys_alt;
+  uint32_t* vout = vals_alt;
+  if (rts) {
+    uint32_t* counts = (uint32_t*)tmp;
+    uint32_t* starts = counts + kRadix * nblk;
+    void* stmp = (void*)(((uintptr_t)(starts + kRadix * nblk) + 255) & ~(uintptr_t)255);
+    for (int p = 0; p < npass; ++p) {
+      const int b = begin_bit + p * kRadixBits;
+      const int nbits = std::min(kRadixBits, end_bit - b);
+      if (items == 16)
+        hipLaunchKernelGGL(k_rs_count<16>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, d_n,
+                           nmax, b, nbits, counts, nblk);
+      else
+        hipLaunchKernelGGL(k_rs_count<8>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, d_n,
+                           nmax, b, nbits, counts, nblk);
+      scan_excl_u32(counts, nullptr, starts, nullptr, kRadix * nblk, nullptr, stmp, st);
+      if (items == 16)
+        hipLaunchKernelGGL((k_os_pass<16, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
+                           vin, kout, vout, d_n, nmax, b, nbits, nullptr, nullptr, nullptr, starts,
+                           nblk);
+      else
+        hipLaunchKernelGGL((k_os_pass<8, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
+                           vin, kout, vout, d_n, nmax, b, nbits, nullptr, nullptr, nullptr, starts,
+                           nblk);
+      uint32_t* tt;
+      tt = kin; kin = kout; kout = tt;
+      tt = vin; vin = vout; vout = tt;
+    }
+    return npass & 1;
+  }
   uint32_t* ghist = (uint32_t*)tmp;
   unsigned long long* status = (unsigned long long*)(ghist + npass * kRadix);
   uint32_t* tickets = (uint32_t*)(status + npass * nblk * kRadix);
@@ -395,21 +478,17 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
   const int hgrid = (int)std::min<int64_t>((nmax + 4095) / 4096, kHistBlocks);
   hipLaunchKernelGGL(k_os_hist, dim3(hgrid), dim3(kBlock), 0, st, keys, d_n, nmax, begin_bit,
                      end_bit, ghist);
-  uint32_t* kin = keys;
-  uint32_t* vin = vals;
-  uint32_t* kout = keys_alt;
-  uint32_t* vout = vals_alt;
   for (int p = 0; p < npass; ++p) {
     const int b = begin_bit + p * kRadixBits;
     const int nbits = std::min(kRadixBits, end_bit - b);
     if (items == 16)
-      hipLaunchKernelGGL(k_os_pass<16>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, vin, kout,
-                         vout, d_n, nmax, b, nbits, ghist + p * kRadix,
-                         status + (int64_t)p * nblk * kRadix, tickets + p);
+      hipLaunchKernelGGL((k_os_pass<16, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
+                         vin, kout, vout, d_n, nmax, b, nbits, ghist + p * kRadix,
+                         status + (int64_t)p * nblk * kRadix, tickets + p, nullptr, nblk);
     else
-      hipLaunchKernelGGL(k_os_pass<8>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, vin, kout,
-                         vout, d_n, nmax, b, nbits, ghist + p * kRadix,
-                         status + (int64_t)p * nblk * kRadix, tickets + p);
+      hipLaunchKernelGGL((k_os_pass<8, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
+                         vin, kout, vout, d_n, nmax, b, nbits, ghist + p * kRadix,
+                         status + (int64_t)p * nblk * kRadix, tickets + p, nullptr, nblk);
     uint32_t* tt;
     tt = kin; kin = kout; kout = tt;
     tt = vin; vin = vout; vout = tt;

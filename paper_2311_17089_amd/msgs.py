@@ -87,6 +87,8 @@ EXPORTS = {
     "msgs_render": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p], C.c_int),
     "msgs_render_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_debug_sort_pairs": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
+                               C.c_int, C.c_void_p], C.c_int),
     "msgs_render_backward_views": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                                     C.c_void_p], C.c_int),
     "msgs_frame_release": ([C.c_void_p], C.c_int),
@@ -344,6 +346,19 @@ def render_backward_views(ctx: Context, frames, dL_drgbs, stream=None,
     check(lib().msgs_render_backward_views(ctx.h, fa, da, len(frames), C.byref(gs),
                                            C.c_void_p(_stream(stream))))
     return g
+
+
+def debug_sort_pairs(ctx: Context, keys: torch.Tensor, vals: torch.Tensor, begin_bit=0, end_bit=32,
+                     d_n: Optional[torch.Tensor] = None, stream=None):
+    """Sort (keys, vals) (int32 device tensors holding u32 bit patterns) in place
+    by key bits [begin_bit, end_bit) with the library's stable radix sort."""
+    assert keys.is_cuda and vals.is_cuda and keys.numel() == vals.numel()
+    assert keys.dtype == torch.int32 and vals.dtype == torch.int32
+    assert keys.is_contiguous() and vals.is_contiguous()
+    dn = C.c_void_p(d_n.data_ptr()) if d_n is not None else None
+    check(lib().msgs_debug_sort_pairs(ctx.h, C.c_void_p(keys.data_ptr()),
+                                      C.c_void_p(vals.data_ptr()), dn, keys.numel(), begin_bit,
+                                      end_bit, C.c_void_p(_stream(stream))))
 
 
 def debug_exp(x: torch.Tensor, stream=None) -> torch.Tensor:
