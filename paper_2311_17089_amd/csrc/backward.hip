@@ -200,7 +200,11 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       const float qxx = dx * dx, qyy = dy * dy, qxy = dx * dy;
       const float e = -0.5f * (a.z * qxx + b.x * qyy);
       const float power = e - a.w * qxy;
-      const float ex = exp_c(power);
+      // exp of a power clamped at -100: the entries that contribute have
+      // power >= -(lnq + 2^-8) > -6 and see the forward's value; for the rest
+      // it stays finite (a Gaussian centre far outside the image makes the
+      // power of order -1e12), so that the zero factors below give zeros
+      const float ex = exp_c(fmaxf(power, -100.0f));
       const float ar = b.y * ex;
       const bool contrib = pos < last && !(power > 0.0f || power < b.z) && !(ar < kAlphaMin);
       const float c0 = b.w, c1 = c.x, c2 = c.y;
@@ -209,18 +213,20 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       // reciprocal (1 ulp) replaces the correctly rounded division
       const float om = __builtin_amdgcn_rcpf(1.0f - al);
       const float Tb = T * om;
-      const float w = al * Tb;
+      // lanes that do not contribute get w = 0 and dar = 0, which zero all
+      // nine partials and leave B unchanged
+      const float w = contrib ? al * Tb : 0.0f;
       float g[kNP];
       g[6] = d0 * w;
       g[7] = d1 * w;
       g[8] = d2 * w;
       const float dal = d0 * (c0 * Tb - B0 * om) + d1 * (c1 * Tb - B1 * om) +
                         d2 * (c2 * Tb - B2 * om);
-      B0 = contrib ? B0 + c0 * w : B0;
-      B1 = contrib ? B1 + c1 * w : B1;
-      B2 = contrib ? B2 + c2 * w : B2;
+      B0 = B0 + c0 * w;
+      B1 = B1 + c1 * w;
+      B2 = B2 + c2 * w;
       T = contrib ? Tb : T;
-      const float dar = ar > kAlphaMax ? 0.0f : dal;
+      const float dar = (ar > kAlphaMax || !contrib) ? 0.0f : dal;
       g[5] = dar * ex;
       const float dp = dar * ar;
       g[2] = dp * (-0.5f * qxx);
@@ -229,10 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       g[0] = dp * (a.z * dx + a.w * dy);
       g[1] = dp * (b.x * dy + a.w * dx);
       if (__ballot(contrib)) {
-        float sm[kNP];
-#pragma unroll
-        for (int q = 0; q < kNP; ++q) sm[q] = contrib ? g[q] : 0.0f;
-        const float tot = wave_reduce9(sm, lane);
+        const float tot = wave_reduce9(g, lane);
         const int q = slot_q(lane & 15);
         if (lane < 16 && q < kNP) red[q][wave][j] = tot;
       } else if (lane == 0) {
