@@ -577,7 +577,10 @@ __global__ __launch_bounds__(kBlock) void k_chain_views(SceneView s, ChainViews 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 void launch_backward_zero(const BwdArgs& a, hipStream_t st) {
-  if (a.n_inst > 0) launch_fill_u32(a.wmask, (a.n_inst + 31) / 32, 0u, st);
+  ZeroList z;
+  z.add(a.nbig, 1);
+  z.add(a.wmask, (a.n_inst + 31) / 32);
+  launch_zero(z, st);
 }
 
 void launch_backward_blend(const BwdArgs& a, hipStream_t st) {

@@ -18,6 +18,8 @@
 //              quadrant, packed in order into the wave's LDS buffer; branch-free
 //              front-to-back compositing with per-wave early exit; the next
 //              chunk's gathers in flight meanwhile; XCD-aware tile order.
+#include <algorithm>
+
 #include "msgs_device.hpp"
 #include "msgs_kernels.hpp"
 
@@ -491,6 +493,24 @@ __global__ void k_cap_clamp(unsigned long long* ctr, unsigned long long cap) {
 
 void launch_cap_clamp(unsigned long long* ctr, unsigned long long cap, hipStream_t st) {
   hipLaunchKernelGGL(k_cap_clamp, dim3(1), dim3(64), 0, st, ctr, cap);
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(ZeroList z, int64_t total) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * kBlock) {
+    int64_t r = i;
+    int sg = 0;
+    while (sg < z.nseg - 1 && r >= z.n[sg]) r -= z.n[sg++];
+    z.p[sg][r] = 0u;
+  }
+}
+
+void launch_zero(const ZeroList& z, hipStream_t st) {
+  int64_t total = 0;
+  for (int i = 0; i < z.nseg; ++i) total += z.n[i];
+  if (total == 0) return;
+  const int64_t g = std::min<int64_t>(grid_for(total), 2048);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(kBlock), 0, st, z, total);
 }
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {

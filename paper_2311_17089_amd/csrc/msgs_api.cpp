@@ -146,7 +146,8 @@ int render_phase1(msgs_frame* f) {
   tmp.add(&f->dkeys[0], n * 4);
   tmp.add(&f->dkeys[1], n * 4);
   tmp.add(&f->dvals_alt, n * 4);
-  tmp.add(&f->scan_tmp, std::max(scan_tmp_bytes(n), scan_tmp_bytes(nb)));
+  tmp.add(&f->scan_tmp, scan_tmp_bytes(nb));
+  tmp.add(&f->scan_tmp2, scan_tmp_bytes(n));
   tmp.add(&f->sort_tmp, radix_tmp_bytes(n, radix_passes(0, 32)));
   int rc = keep.alloc(f->ctx, st);
   if (rc != MSGS_OK) return rc;
@@ -157,17 +158,23 @@ int render_phase1(msgs_frame* f) {
   uint32_t* vin = even ? f->order : f->dvals_alt;
   uint32_t* valt = even ? f->dvals_alt : f->order;
   dv0 = vin;
-  launch_fill_u32((uint32_t*)f->ctr, 2 * (8 + kSlotW * kCtrSlots), 0u, st);
+  // counters and every status word of the phase, cleared by one launch
+  ZeroList z;
+  z.add(f->ctr, 2 * (8 + kSlotW * kCtrSlots));
+  z.add(f->scan_tmp, scan_zero_words(nb));
+  z.add(f->scan_tmp2, scan_zero_words(n));
+  z.add(f->sort_tmp, radix_zero_words(n, radix_passes(0, 32)));
+  launch_zero(z, st);
   mark(f, 0);
   launch_project(f->scene->view, v, f->sel, f->count, f->depthkey, f->rec, f->rect, f->blk_vis,
                  f->ctr + 8, st);
-  scan_excl_u32(f->blk_vis, nullptr, f->blk_off, nullptr, nb, &f->ctr[2], f->scan_tmp, st);
+  scan_excl_u32(f->blk_vis, nullptr, f->blk_off, nullptr, nb, &f->ctr[2], f->scan_tmp, st, true);
   launch_compact(f->count, f->depthkey, n, f->blk_off, f->dkeys[0], dv0, st);
   mark(f, 1);
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
-  radix_sort_pairs(f->dkeys[0], vin, f->dkeys[1], valt, d_nvis, n, 0, 32, f->sort_tmp, st);
+  radix_sort_pairs(f->dkeys[0], vin, f->dkeys[1], valt, d_nvis, n, 0, 32, f->sort_tmp, st, true);
   mark(f, 2);
-  scan_excl_u32(f->count, f->order, f->off_d, d_nvis, n, &f->ctr[3], f->scan_tmp, st);
+  scan_excl_u32(f->count, f->order, f->off_d, d_nvis, n, &f->ctr[3], f->scan_tmp2, st, true);
   mark(f, 3);
   return MSGS_OK;
 }
@@ -201,6 +208,10 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   uint32_t* k1 = even ? kb : ka;
   uint32_t* v1 = even ? vb : va;
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
+  ZeroList z;
+  z.add(f->ranges, (int64_t)ntile * 2);
+  z.add(stmp, radix_zero_words(I, radix_passes(0, bits)));
+  launch_zero(z, st);
   mark(f, 4);
   // fixed capacity: the instance count stays on the device (ctr[7] = the
   // instances that fit); emission, sort and ranges never pass the capacity
@@ -208,11 +219,10 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   launch_emit(f->order, f->off_d, d_nvis, n, f->count, f->rect, v.Tx, k0, v0, f->emit_base,
               f->capacity ? (uint32_t)I : 0xFFFFFFFFu, st);
   mark(f, 5);
-  radix_sort_pairs(k0, v0, k1, v1, d_inst, I, 0, bits, stmp, st);
+  radix_sort_pairs(k0, v0, k1, v1, d_inst, I, 0, bits, stmp, st, true);
   mark(f, 6);
   f->tkeys = ka;
   f->tvals = va;
-  launch_fill_u32((uint32_t*)f->ranges, (int64_t)ntile * 2, 0u, st);
   launch_ranges(f->tkeys, d_inst, (uint32_t)I, f->ranges, st);
   mark(f, 7);
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
@@ -224,7 +234,7 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   f->tmp_block = nullptr;
   f->blk_vis = f->blk_off = f->dvals_alt = nullptr;
   f->dkeys[0] = f->dkeys[1] = nullptr;
-  f->scan_tmp = f->sort_tmp = nullptr;
+  f->scan_tmp = f->scan_tmp2 = f->sort_tmp = nullptr;
   return MSGS_OK;
 }
 
@@ -596,7 +606,6 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   tmp.add(&a.nbig, 4);
   int rc = tmp.alloc(c, st);
   if (rc == MSGS_OK) {
-    launch_fill_u32(a.nbig, 1, 0u, st);
     msgs_frame* fm = const_cast<msgs_frame*>(f);
     if (fm->profile) (void)hipEventRecord(fm->ev[9], st);
     launch_backward_zero(a, st);
@@ -673,7 +682,6 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
     a.gsum = gsum + (size_t)12 * (size_t)n * (size_t)i;
     a.big = big;
     a.nbig = nbig;
-    launch_fill_u32(nbig, 1, 0u, st);
     launch_backward_zero(a, st);
     launch_backward_blend(a, st);
     launch_backward_segsum(a, st);

@@ -94,6 +94,7 @@ struct msgs_frame {
   uint32_t* dkeys[2] = {nullptr, nullptr};
   uint32_t* dvals_alt = nullptr;
   void* scan_tmp = nullptr;
+  void* scan_tmp2 = nullptr;
   void* sort_tmp = nullptr;
 };
 

@@ -20,6 +20,22 @@ void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_n
                  uint32_t* tvals, uint32_t* emit_base, uint32_t cap, hipStream_t st);
 void launch_cap_clamp(unsigned long long* ctr, unsigned long long cap, hipStream_t st);
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+// Up to kZeroSegs device regions cleared by one launch (the counters, status
+// words and flags that a render or a backward pass needs zeroed up front).
+constexpr int kZeroSegs = 8;
+struct ZeroList {
+  uint32_t* p[kZeroSegs] = {};
+  int64_t n[kZeroSegs] = {};
+  int nseg = 0;
+  void add(void* ptr, int64_t words) {
+    if (words > 0 && nseg < kZeroSegs) {
+      p[nseg] = (uint32_t*)ptr;
+      n[nseg] = words;
+      ++nseg;
+    }
+  }
+};
+void launch_zero(const ZeroList& z, hipStream_t st);
 void launch_ranges(const uint32_t* tkeys, const uint32_t* d_n, uint32_t nmax, uint2* ranges,
                    hipStream_t st);
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
@@ -34,14 +50,19 @@ size_t scan_tmp_bytes(int64_t nmax);
 // Exclusive scan of x[0..n) into out[0..nmax) (zeros past n), x[i] = in[i] or
 // in[gather[i]]; n = *d_n when d_n is non-null, else nmax.  *total (device
 // u64) receives the sum.  One kernel (decoupled look-back).
+// zeroed: the caller has cleared the first scan_zero_words(nmax) words of tmp.
 void scan_excl_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const uint32_t* d_n,
-                   int64_t nmax, unsigned long long* total, void* tmp, hipStream_t st);
+                   int64_t nmax, unsigned long long* total, void* tmp, hipStream_t st,
+                   bool zeroed = false);
+int64_t scan_zero_words(int64_t nmax);
 size_t radix_tmp_bytes(int64_t nmax, int npass);
 // Stable LSD sort of pairs by key bits [begin_bit, end_bit).  Returns 1 when
-// the result ended in keys_alt / vals_alt, 0 when in keys / vals.
+// the result ended in keys_alt / vals_alt, 0 when in keys / vals.  zeroed: the
+// caller has cleared the first radix_zero_words(nmax, npass) words of tmp.
 int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                      const uint32_t* d_n, int64_t nmax, int begin_bit, int end_bit, void* tmp,
-                     hipStream_t st);
+                     hipStream_t st, bool zeroed = false);
+int64_t radix_zero_words(int64_t nmax, int npass);
 
 // backward.hip
 struct BwdArgs {
@@ -64,7 +85,7 @@ struct BwdArgs {
   int64_t n_inst;
   float* gsum;              // [n][12] per-Gaussian sums (9 used)
   uint32_t* big;            // [n] Gaussians with many tiles
-  uint32_t* nbig;           // device counter, zeroed by the caller
+  uint32_t* nbig;           // device counter (zeroed by launch_backward_zero)
   float* g_means;
   float* g_scales;
   float* g_quats;
@@ -72,7 +93,7 @@ struct BwdArgs {
   float* g_sh;
   int accumulate;           // add into the gradient planes instead of writing them
 };
-void launch_backward_zero(const BwdArgs& a, hipStream_t st);
+void launch_backward_zero(const BwdArgs& a, hipStream_t st);    // clears wmask and nbig
 void launch_backward_blend(const BwdArgs& a, hipStream_t st);
 void launch_backward_chain(const BwdArgs& a, hipStream_t st);   // segment sums + chain rule
 void launch_backward_segsum(const BwdArgs& a, hipStream_t st);  // segment sums into a.gsum

@@ -403,16 +403,22 @@ size_t scan_tmp_bytes(int64_t nmax) {
   return (size_t)(nb > 0 ? nb : 1) * 8 + 256;
 }
 
+int64_t scan_zero_words(int64_t nmax) {
+  const int64_t nb = (nmax + kScanTile - 1) / kScanTile;
+  return nb > 0 ? 2 * nb + 2 : 0;
+}
+
 void scan_excl_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, const uint32_t* d_n,
-                   int64_t nmax, unsigned long long* total, void* tmp, hipStream_t st) {
+                   int64_t nmax, unsigned long long* total, void* tmp, hipStream_t st,
+                   bool zeroed) {
   const int64_t nb = (nmax + kScanTile - 1) / kScanTile;
   unsigned long long* status = (unsigned long long*)tmp;
   uint32_t* ticket = (uint32_t*)(status + (nb > 0 ? nb : 1));
   if (nb == 0) {
-    launch_fill_u32((uint32_t*)total, 2, 0u, st);
+    if (total) launch_fill_u32((uint32_t*)total, 2, 0u, st);
     return;
   }
-  launch_fill_u32((uint32_t*)status, 2 * nb + 2, 0u, st);
+  if (!zeroed) launch_fill_u32((uint32_t*)status, scan_zero_words(nmax), 0u, st);
   hipLaunchKernelGGL(k_scan_lb, dim3((unsigned)nb), dim3(kBlock), 0, st, in, gather, d_n, nmax,
                      out, total, status, ticket);
 }
@@ -420,32 +426,49 @@ void scan_excl_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, co
 // Tiles from which a sort pass switches to reduce-then-scan.
 constexpr int64_t kRtsMinTiles = 512;
 
+// Layout of the temporary block.  Onesweep: [global histograms][status words
+// of every pass][tickets], all zeroed.  Reduce-then-scan: [scan status of every
+// pass (zeroed), each rounded to 256 bytes][digit counts][digit starts].
+static inline int64_t sort_tiles(int64_t nmax) {
+  const int64_t tile = (int64_t)kBlock * sort_items(nmax);
+  return (nmax + tile - 1) / tile;
+}
+static inline size_t rts_scan_stride(int64_t nblk) {
+  return (scan_tmp_bytes(kRadix * nblk) + 255) & ~(size_t)255;
+}
+
+int64_t radix_zero_words(int64_t nmax, int npass) {
+  if (nmax == 0 || npass == 0) return 0;
+  const int64_t nblk = sort_tiles(nmax);
+  if (nblk >= kRtsMinTiles) return (int64_t)(npass * rts_scan_stride(nblk) / 4);
+  return npass * kRadix + 2 * npass * nblk * kRadix + 64;
+}
+
 size_t radix_tmp_bytes(int64_t nmax, int npass) {
-  const int items = sort_items(nmax);
-  const int64_t nblk = (nmax + kBlock * items - 1) / (kBlock * items);
-  const int64_t nb = nblk > 0 ? nblk : 1;
-  const size_t onesweep = (size_t)npass * kRadix * 4 + (size_t)npass * nb * kRadix * 8 + 64 * 4;
-  const size_t rts = (size_t)2 * kRadix * nb * 4 + 256 + scan_tmp_bytes(kRadix * nb);
+  const int64_t nblk = std::max<int64_t>(sort_tiles(nmax), 1);
+  const size_t onesweep =
+      (size_t)npass * kRadix * 4 + (size_t)npass * nblk * kRadix * 8 + 64 * 4;
+  const size_t rts = (size_t)npass * rts_scan_stride(nblk) + (size_t)2 * kRadix * nblk * 4;
   return std::max(onesweep, rts);
 }
 
 int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                      const uint32_t* d_n, int64_t nmax, int begin_bit, int end_bit, void* tmp,
-                     hipStream_t st) {
+                     hipStream_t st, bool zeroed) {
   if (nmax == 0 || end_bit <= begin_bit) return 0;
   const int npass = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
   const int items = sort_items(nmax);
-  const int tile = kBlock * items;
-  const int64_t nblk = (nmax + tile - 1) / tile;
+  const int64_t nblk = sort_tiles(nmax);
   const bool rts = nblk >= kRtsMinTiles;
   uint32_t* kin = keys;
   uint32_t* vin = vals;
   uint32_t* kout = keys_alt;
   uint32_t* vout = vals_alt;
+  if (!zeroed) launch_fill_u32((uint32_t*)tmp, radix_zero_words(nmax, npass), 0u, st);
   if (rts) {
-    uint32_t* counts = (uint32_t*)tmp;
+    const size_t stride = rts_scan_stride(nblk);
+    uint32_t* counts = (uint32_t*)((char*)tmp + npass * stride);
     uint32_t* starts = counts + kRadix * nblk;
-    void* stmp = (void*)(((uintptr_t)(starts + kRadix * nblk) + 255) & ~(uintptr_t)255);
     for (int p = 0; p < npass; ++p) {
       const int b = begin_bit + p * kRadixBits;
       const int nbits = std::min(kRadixBits, end_bit - b);
@@ -455,7 +478,8 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
       else
         hipLaunchKernelGGL(k_rs_count<8>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, d_n,
                            nmax, b, nbits, counts, nblk);
-      scan_excl_u32(counts, nullptr, starts, nullptr, kRadix * nblk, nullptr, stmp, st);
+      scan_excl_u32(counts, nullptr, starts, nullptr, kRadix * nblk, nullptr,
+                    (char*)tmp + p * stride, st, true);
       if (items == 16)
         hipLaunchKernelGGL((k_os_pass<16, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                            vin, kout, vout, d_n, nmax, b, nbits, nullptr, nullptr, nullptr, starts,
@@ -473,8 +497,6 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
   uint32_t* ghist = (uint32_t*)tmp;
   unsigned long long* status = (unsigned long long*)(ghist + npass * kRadix);
   uint32_t* tickets = (uint32_t*)(status + npass * nblk * kRadix);
-  const int64_t zero_words = npass * kRadix + 2 * npass * nblk * kRadix + 64;
-  launch_fill_u32((uint32_t*)tmp, zero_words, 0u, st);
   const int hgrid = (int)std::min<int64_t>((nmax + 4095) / 4096, kHistBlocks);
   hipLaunchKernelGGL(k_os_hist, dim3(hgrid), dim3(kBlock), 0, st, keys, d_n, nmax, begin_bit,
                      end_bit, ghist);
