@@ -224,8 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_os_hist(const uint32_t* keys, const 
 }
 
 // Digit counts of one tile for the reduce-then-scan pass: counts[d * nblk + t]
-// (digit-major, so that one exclusive scan of the whole array gives every
-// (digit, tile) its global start).  Tiles past the input count nothing.
+// (digit-major: row d holds digit d's count in every tile).  Tiles past the
+// input write nothing; the row scan reads only the tiles that hold items.
 template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* keys, const uint32_t* d_n,
                                                      int64_t nmax, int shift, int nbits,
@@ -233,12 +233,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* keys, const
   constexpr int TILE = kBlock * ITEMS;
   __shared__ uint32_t h[kBlock / 64][kRadix];
   const int wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) h[w][threadIdx.x] = 0;
-  __syncthreads();
   const int64_t n = d_n ? (int64_t)*d_n : nmax;
   const int64_t t = blockIdx.x;
   const int64_t tbase = t * TILE;
+  if (tbase >= n) return;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) h[w][threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t mask = (1u << nbits) - 1u;
   uint32_t k_[ITEMS];
 #pragma unroll
@@ -256,12 +257,47 @@ __global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* keys, const
   counts[(int64_t)threadIdx.x * nblk + t] = c;
 }
 
+// Exclusive scan of row d of the digit counts over the tiles that hold items
+// (one workgroup per digit), and the row total: starts[d * nblk + t] is then
+// the position of digit d's first item of tile t among all items of digit d.
+constexpr int kRowItems = 4;
+__global__ __launch_bounds__(kBlock) void k_rs_rowscan(const uint32_t* counts, uint32_t* starts,
+                                                       uint32_t* rowtot, const uint32_t* d_n,
+                                                       int64_t nmax, int tile, int64_t nblk) {
+  __shared__ uint32_t wtot[kBlock / 64];
+  const int64_t n = d_n ? (int64_t)*d_n : nmax;
+  const int64_t nt = (n + tile - 1) / tile;
+  const uint32_t* row = counts + (int64_t)blockIdx.x * nblk;
+  uint32_t* out = starts + (int64_t)blockIdx.x * nblk;
+  uint32_t run = 0;
+  for (int64_t c0 = 0; c0 < nt; c0 += (int64_t)kBlock * kRowItems) {
+    const int64_t i0 = c0 + (int64_t)threadIdx.x * kRowItems;
+    uint32_t v[kRowItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int r = 0; r < kRowItems; ++r) {
+      v[r] = i0 + r < nt ? row[i0 + r] : 0u;
+      sum += v[r];
+    }
+    uint32_t ctot;
+    uint32_t e = run + block_excl_scan(sum, wtot, ctot);
+#pragma unroll
+    for (int r = 0; r < kRowItems; ++r) {
+      if (i0 + r < nt) out[i0 + r] = e;
+      e += v[r];
+    }
+    run += ctot;
+  }
+  if (threadIdx.x == 0) rowtot[blockIdx.x] = run;
+}
+
 // One pass of the sort.  RTS = false (onesweep): the tile's digit starts come
 // from the global histogram and a decoupled look-back over the tiles before
-// it.  RTS = true (reduce-then-scan): they are read from `starts`, the
-// exclusive scan of k_rs_count's digit-major counts, so no tile waits on
-// another (on a chip whose L2s are per XCD every look-back step is a trip to
-// memory, which long chains of tiles pay for one after another).
+// it.  RTS = true (reduce-then-scan): they are the exclusive scan of the digit
+// totals (`hist` holds them: the row totals of k_rs_rowscan) plus the row
+// scan `starts`, so no tile waits on another (on a chip whose L2s are per XCD
+// every look-back step is a trip to memory, which long chains of tiles pay
+// for one after another).
 template <int ITEMS, bool RTS>
 __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
                                                     const uint32_t* vals_in, uint32_t* keys_out,
@@ -302,13 +338,10 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) k_[i] = i * 64 + lane < remw ? kin_w[i * 64 + lane] : 0u;
   // global start of every digit: exclusive scan of the digit totals
-  uint32_t htot, hd = 0, gs = 0;
-  if (!RTS) {
-    hd = hist[threadIdx.x];
-    gs = block_excl_scan(hd, wtot, htot);
-  } else {
-    gs = starts[(int64_t)threadIdx.x * nblk + t];
-  }
+  uint32_t htot;
+  const uint32_t hd = hist[threadIdx.x];
+  uint32_t gs = block_excl_scan(hd, wtot, htot);
+  if (RTS) gs += starts[(int64_t)threadIdx.x * nblk + t];
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const bool valid = i * 64 + lane < remw;
@@ -427,20 +460,17 @@ void scan_excl_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, co
 constexpr int64_t kRtsMinTiles = 512;
 
 // Layout of the temporary block.  Onesweep: [global histograms][status words
-// of every pass][tickets], all zeroed.  Reduce-then-scan: [scan status of every
-// pass (zeroed), each rounded to 256 bytes][digit counts][digit starts].
+// of every pass][tickets], all zeroed.  Reduce-then-scan: [digit totals][digit
+// counts][digit starts], nothing to zero.
 static inline int64_t sort_tiles(int64_t nmax) {
   const int64_t tile = (int64_t)kBlock * sort_items(nmax);
   return (nmax + tile - 1) / tile;
-}
-static inline size_t rts_scan_stride(int64_t nblk) {
-  return (scan_tmp_bytes(kRadix * nblk) + 255) & ~(size_t)255;
 }
 
 int64_t radix_zero_words(int64_t nmax, int npass) {
   if (nmax == 0 || npass == 0) return 0;
   const int64_t nblk = sort_tiles(nmax);
-  if (nblk >= kRtsMinTiles) return (int64_t)(npass * rts_scan_stride(nblk) / 4);
+  if (nblk >= kRtsMinTiles) return 0;
   return npass * kRadix + 2 * npass * nblk * kRadix + 64;
 }
 
@@ -448,7 +478,7 @@ size_t radix_tmp_bytes(int64_t nmax, int npass) {
   const int64_t nblk = std::max<int64_t>(sort_tiles(nmax), 1);
   const size_t onesweep =
       (size_t)npass * kRadix * 4 + (size_t)npass * nblk * kRadix * 8 + 64 * 4;
-  const size_t rts = (size_t)npass * rts_scan_stride(nblk) + (size_t)2 * kRadix * nblk * 4;
+  const size_t rts = (size_t)kRadix * 4 + (size_t)2 * kRadix * nblk * 4;
   return std::max(onesweep, rts);
 }
 
@@ -466,8 +496,8 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
   uint32_t* vout = vals_alt;
   if (!zeroed) launch_fill_u32((uint32_t*)tmp, radix_zero_words(nmax, npass), 0u, st);
   if (rts) {
-    const size_t stride = rts_scan_stride(nblk);
-    uint32_t* counts = (uint32_t*)((char*)tmp + npass * stride);
+    uint32_t* rowtot = (uint32_t*)tmp;
+    uint32_t* counts = rowtot + kRadix;
     uint32_t* starts = counts + kRadix * nblk;
     for (int p = 0; p < npass; ++p) {
       const int b = begin_bit + p * kRadixBits;
@@ -478,15 +508,15 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
       else
         hipLaunchKernelGGL(k_rs_count<8>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, d_n,
                            nmax, b, nbits, counts, nblk);
-      scan_excl_u32(counts, nullptr, starts, nullptr, kRadix * nblk, nullptr,
-                    (char*)tmp + p * stride, st, true);
+      hipLaunchKernelGGL(k_rs_rowscan, dim3(kRadix), dim3(kBlock), 0, st, counts, starts, rowtot,
+                         d_n, nmax, kBlock * items, nblk);
       if (items == 16)
         hipLaunchKernelGGL((k_os_pass<16, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
-                           vin, kout, vout, d_n, nmax, b, nbits, nullptr, nullptr, nullptr, starts,
+                           vin, kout, vout, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
                            nblk);
       else
         hipLaunchKernelGGL((k_os_pass<8, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
-                           vin, kout, vout, d_n, nmax, b, nbits, nullptr, nullptr, nullptr, starts,
+                           vin, kout, vout, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
                            nblk);
       uint32_t* tt;
       tt = kin; kin = kout; kout = tt;

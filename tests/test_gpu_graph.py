@@ -66,7 +66,9 @@ def test_fixed_capacity_matches_exact_and_reports_overflow():
     dsc.close()
 
 
-def test_captured_training_step_replays_exactly():
+@pytest.mark.parametrize("views_backward", [False, True])
+def test_captured_training_step_replays_exactly(views_backward):
+    _say(f"  captured step, multi-view backward {views_backward}")
     ctx = M.Context(0)
     dsc = _scene(ctx)
     views = _views()
@@ -83,13 +85,17 @@ def test_captured_training_step_replays_exactly():
     frames = []
 
     def step():
-        for k in NAMES:
-            grads[k].copy_(zeros[k])
+        if not views_backward:
+            for k in NAMES:
+                grads[k].copy_(zeros[k])
         fs = []
         for (cam, d), dl, cap, o in zip(views, dls, caps, outs):
             _, fr = M.render(ctx, dsc, cam, downscale=d, keep_frame=True, capacity=cap, out=o)
-            M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
+            if not views_backward:
+                M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
             fs.append(fr)
+        if views_backward:
+            M.render_backward_views(ctx, fs, dls, grads=grads)
         return fs
 
     side = torch.cuda.Stream()
