@@ -20,6 +20,8 @@
 //  k_chain       chain rule per Gaussian from (u, conic, sigma, colour) to the
 //                scene parameters (means, linear scales, raw quaternion,
 //                opacity, SH), recomputing the projection of the forward.
+#include <algorithm>
+
 #include "msgs_device.hpp"
 #include "msgs_kernels.hpp"
 
@@ -285,11 +287,12 @@ __device__ __forceinline__ void store3(float* gsum, int64_t k, const float* s) {
 
 // Per-Gaussian sums of the partials over the emission range, Gaussians in
 // emission order; those with more than kSmallSeg tiles are queued for
-// k_seg_big.
+// k_seg_big.  Ranges are clipped to `cap` (the tile lists of a fixed-capacity
+// frame end there, also when the frame overflowed).
 __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int64_t n_vis,
                                                       const uint32_t* d_nvis,
                                                       const uint32_t* count,
-                                                      const uint32_t* emit_base,
+                                                      const uint32_t* emit_base, uint32_t cap,
                                                       const float* partial, const uint32_t* wmask,
                                                       float* gsum, uint32_t* big, uint32_t* nbig) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -304,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
 #pragma unroll
   for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
   // only the slots whose partial was written (bit set) are read, in order
-  const uint32_t e0 = emit_base[k], e1 = e0 + c;
+  const uint32_t e0 = min(emit_base[k], cap), e1 = min(emit_base[k] + c, cap);
   const float4* P = (const float4*)partial;
   for (uint32_t w0 = e0 & ~31u; w0 < e1; w0 += 32u) {
     uint32_t bits = wmask[w0 >> 5];
@@ -321,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
-                                                    const uint32_t* emit_base,
+                                                    const uint32_t* emit_base, uint32_t cap,
                                                     const float* partial, const uint32_t* wmask,
                                                     float* gsum, const uint32_t* big,
                                                     const uint32_t* nbig) {
@@ -330,8 +333,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
   const uint32_t m = *nbig;
   for (uint32_t i = blockIdx.x; i < m; i += gridDim.x) {
     const uint32_t k = big[i];
-    const uint32_t c = count[k];
-    const uint32_t e0 = emit_base[k];
+    const uint32_t e0 = min(emit_base[k], cap);
+    const uint32_t c = min(emit_base[k] + count[k], cap) - e0;
     const float4* P = (const float4*)partial;
     float s[kNP];
 #pragma unroll
@@ -607,10 +610,12 @@ static void launch_chain_d(const BwdArgs& a, dim3 g, dim3 b, hipStream_t st) {
 
 void launch_backward_segsum(const BwdArgs& a, hipStream_t st) {
   if (a.s.n == 0 || a.n_vis == 0) return;
+  const uint32_t cap = (uint32_t)std::min<int64_t>(a.n_inst, 0xFFFFFFFFll);
   hipLaunchKernelGGL(k_seg_small, dim3(grid_for(a.n_vis)), dim3(kBlock), 0, st, a.order, a.n_vis,
-                     a.d_nvis, a.count, a.emit_base, a.partial, a.wmask, a.gsum, a.big, a.nbig);
-  hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, a.partial,
-                     a.wmask, a.gsum, a.big, a.nbig);
+                     a.d_nvis, a.count, a.emit_base, cap, a.partial, a.wmask, a.gsum, a.big,
+                     a.nbig);
+  hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, cap,
+                     a.partial, a.wmask, a.gsum, a.big, a.nbig);
 }
 
 void launch_backward_chain(const BwdArgs& a, hipStream_t st) {

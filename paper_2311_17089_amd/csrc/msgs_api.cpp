@@ -671,9 +671,9 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
     a.emit_base = f->emit_base;
     a.count = f->count;
     a.order = f->order;
-    a.n_vis = f->n_vis;
+      a.n_vis = f->n_vis;
     a.d_nvis = (const uint32_t*)&f->ctr[2];
-    a.T_final = f->T_final;
+      a.T_final = f->T_final;
     a.n_last = f->n_last;
     a.dL_drgb = dL_drgb[i];
     a.n_inst = f->n_inst;

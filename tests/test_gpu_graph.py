@@ -56,8 +56,13 @@ def test_fixed_capacity_matches_exact_and_reports_overflow():
         for k in NAMES:
             np.testing.assert_array_equal(g0[k].cpu().numpy(), g1[k].cpu().numpy())
         f1.release()
-    # too small a capacity: the frame completes without fault and says so
+    # too small a capacity: the frame and its backward complete without fault
+    # (every per-Gaussian slot range is clipped to the capacity) and the frame
+    # says so
     _, f2 = M.render(ctx, dsc, cam, downscale=d, keep_frame=True, capacity=I // 2)
+    M.render_backward(ctx, f2, dl)
+    M.render_backward_views(ctx, [f2], [dl])
+    torch.cuda.synchronize()
     with pytest.raises(M.MsgsError) as e:
         f2.stats()
     assert e.value.code == M.E_CAPACITY
