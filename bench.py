@@ -161,6 +161,82 @@ def serving_replay(M, G, n_req=512, rate_hz=200.0, inflight=4, selective=True):
             "p50_ms_by_downscale": {str(k): float(np.percentile(v, 50)) for k, v in sorted(per_ds.items())}}
 
 
+def aggregation_bench(M, G, reps=3):
+    """Alg. 1 on the GPU: the level-0 Gaussians of the 3M-Gaussian scene
+    (2,258,824 of them, SH degree 3) and 8 training cameras at radius 3,
+    1920x1080; level 1 (downscale 4, 200^3 voxels) and then level 2 (16,
+    133^3) built on top of it, as msgs.build_levels does.  Timed per level:
+    one aggregate_level call on the resident scene (minimal coverage over the
+    cameras, voxel keys, sort, segmented average pooling, enlargement), device
+    synchronised on both sides."""
+    import dataclasses
+    import torch
+    sc = G.large_scene(3_000_000, 4, 3)
+    keep = sc.level == 0
+    base = dataclasses.replace(sc, n=int(keep.sum()), n_levels=3, means=sc.means[:, keep].copy(),
+                               scales=sc.scales[:, keep].copy(), quats=sc.quats[:, keep].copy(),
+                               opacity=sc.opacity[keep].copy(), sh=sc.sh[:, keep].copy(),
+                               level=sc.level[keep].copy(), s_max=sc.s_max[keep].copy(),
+                               s_min=sc.s_min[keep].copy())
+    cams = G.calibration_cameras(1003, 1920, 1080, 2250.0)
+    ctx = M.Context(0)
+    extent = M.camera_extent(cams)
+    res = {}
+    scene = base
+    for level in (1, 2):
+        dsc = M.DeviceScene(ctx, scene)
+        part = M.aggregate_level(ctx, dsc, cams, level, 2.0, extent)  # warm-up
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            part = M.aggregate_level(ctx, dsc, cams, level, 2.0, extent)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        below = int(scene.n)
+        added = int(part["opacity"].numel())
+        dt = sorted(ts)[len(ts) // 2]
+        res[str(level)] = {"gaussians_below": below, "added": added, "ms": dt * 1e3,
+                           "gaussians_per_s": below / dt, "cameras": len(cams)}
+        host = {k: v.cpu().numpy() for k, v in part.items()}
+        dsc.close()
+        import numpy as np
+        scene = dataclasses.replace(
+            scene, n=scene.n + added,
+            means=np.ascontiguousarray(np.concatenate([scene.means, host["means"]], 1)),
+            scales=np.ascontiguousarray(np.concatenate([scene.scales, host["scales"]], 1)),
+            quats=np.ascontiguousarray(np.concatenate([scene.quats, host["quats"]], 1)),
+            opacity=np.ascontiguousarray(np.concatenate([scene.opacity, host["opacity"]])),
+            sh=np.ascontiguousarray(np.concatenate([scene.sh, host["sh"]], 1)),
+            level=np.concatenate([scene.level, np.full(added, level, np.uint8)]),
+            s_max=np.concatenate([scene.s_max, np.zeros(added, np.float32)]),
+            s_min=np.concatenate([scene.s_min, np.full(added, np.inf, np.float32)]))
+    return {"workload": "level 0 of the 3M-Gaussian scene (2,258,824 Gaussians, SH degree 3), "
+                        "8 cameras at 1920x1080; levels 1 and 2 aggregated in turn", "levels": res}
+
+
+def prefilter_effect(M, ctx, dsc, cam, reps=5):
+    """Projection-stage device time of the C2 frames with the pre-splat coverage
+    bound on and off (the results are identical either way), and how many
+    Gaussians the bound settled before the rotation load and the EWA."""
+    import numpy as np
+    out = {}
+    for ds in DOWNSCALES:
+        row = {}
+        for on in (True, False):
+            us, nf = [], 0
+            for _ in range(reps):
+                _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, profile=True,
+                                 prefilter=on)
+                st = fr.stats()
+                fr.release()
+                us.append(st["stage_us"][0])
+                nf = st["n_prefiltered"]
+            row["on" if on else "off"] = {"project_us": float(np.median(us)), "prefiltered": nf}
+        out[str(ds)] = row
+    return out
+
+
 def training_step(M, G, steps=5, warmup=2):
     """Multi-view training step on the 6M-Gaussian, 5-level scene: 8 views
     (seeded poses on a sphere of radius 2-12), one at each downscale 1, 2, ...,
@@ -292,6 +368,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-training", action="store_true")
+    ap.add_argument("--no-aggregation", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one serial step and a 1 GiB elementwise copy, for HBM counter runs")
@@ -498,6 +575,7 @@ def main():
         "stage_us_per_step": {s: round(v, 2) for s, v in stage_tot.items()},
         "hbm_stages": hbm_stages,
         "per_downscale": per_ds,
+        "prefilter": prefilter_effect(M, ctx, dsc, cam),
     }
     if not args.no_serving:
         print("bench: serving replay (3M-Gaussian scene, 512 requests at 200/s)", file=sys.stderr,
@@ -507,6 +585,10 @@ def main():
     if not args.no_training:
         print("bench: training step (6M Gaussians, 8 views)", file=sys.stderr, flush=True)
         out["training_step"] = training_step(M, G)
+    if not args.no_aggregation:
+        print("bench: aggregation (Alg. 1, 2.26M level-0 Gaussians, 8 cameras)", file=sys.stderr,
+              flush=True)
+        out["aggregation"] = aggregation_bench(M, G)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

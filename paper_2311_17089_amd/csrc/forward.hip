@@ -37,23 +37,22 @@ namespace msgs {
 // sides.  Returns true only when the selection test is certain to fail; the
 // exact path then never runs (no rotation load, no EWA), and the selection
 // mask is the same bit for bit.
-__device__ __forceinline__ bool prefilter_unselected(const SceneView& s, const ViewParams& v,
-                                                     int64_t k, int l, float lnq) {
-  const int64_t n = s.n;
-  const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
+__device__ __forceinline__ bool prefilter_unselected(const ViewParams& v, int n_levels,
+                                                     float mu0, float mu1, float mu2, float s0,
+                                                     float s1, float s2, float smax, float smin,
+                                                     int l, float lnq) {
   const float px = ((v.R[0] * mu0 + v.R[1] * mu1) + v.R[2] * mu2) + v.t[0];
   const float py = ((v.R[3] * mu0 + v.R[4] * mu1) + v.R[5] * mu2) + v.t[1];
   const float pz = ((v.R[6] * mu0 + v.R[7] * mu1) + v.R[8] * mu2) + v.t[2];
   if (!(pz > 1.001f * v.near_z)) return false;  // depth near the plane: exact path
-  const float s0 = s.scales[k], s1 = s.scales[n + k], s2 = s.scales[2 * n + k];
   const float smn = fminf(fminf(s0, s1), s2);
   const float smd = fmaxf(fminf(s0, s1), fminf(fmaxf(s0, s1), s2));
   const float xr = px / pz, yr = py / pz;
   const float flo = fminf(v.fx, v.fy) / pz, fhi = fmaxf(v.fx, v.fy) / pz;
   const float lo = sqrtf(8.0f * lnq) * flo * smn * 0.999f;
   const float hi = sqrtf(16.0f * lnq * (1.0f + (xr * xr + yr * yr))) * fhi * smd * 1.001f;
-  const bool g1_fails = l > 0 && lo > 1.5f * s.s_max[k];
-  const bool g2_fails = l < s.n_levels - 1 && hi < 0.5f * s.s_min[k] && hi < 2.0f;
+  const bool g1_fails = l > 0 && lo > 1.5f * smax;
+  const bool g2_fails = l < n_levels - 1 && hi < 0.5f * smin && hi < 2.0f;
   return g1_fails || g2_fails;
 }
 
@@ -69,29 +68,41 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, u
   int culled = 0;
   if (k < n) {
     Geo g;
+    // every per-Gaussian input of the geometry and the selection, loaded
+    // together (one memory round trip; SH follows for the selected only)
     const float sig = s.opacity[k];
+    const int l = s.level[k];
+    const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
+    const float s0 = s.scales[k], s1 = s.scales[n + k], s2 = s.scales[2 * n + k];
+    const float qw = s.quats[k], qx = s.quats[n + k], qy = s.quats[2 * n + k],
+                qz = s.quats[3 * n + k];
+    const float smax = s.s_max[k], smin = s.s_min[k];
     const float y255 = 255.0f * sig;
     const bool vis = y255 > 1.0f;
     const float lnq = vis ? log_c(y255) : 0.0f;
-    const int l = s.level[k];
     const bool skip = v.prefilter && v.selective && vis && l != v.update_level &&
-                      prefilter_unselected(s, v, k, l, lnq);
+                      prefilter_unselected(v, s.n_levels, mu0, mu1, mu2, s0, s1, s2, smax, smin,
+                                           l, lnq);
     culled = skip ? 1 : 0;
-    const bool front = !skip && project_geo(s, v, k, g);
+    bool front = false;
+    if (!skip) {
+      geo_shape_of(qw, qx, qy, qz, s0, s1, s2, g);
+      front = geo_view(v, mu0, mu1, mu2, g);
+    }
     float S = 0.0f;
     bool sel = false;
     if (front) {
       S = coverage(g.V11, g.V12, g.V22, vis, lnq);
       sel = true;
       if (v.selective) {
-        bool g1 = (l == 0) || (S <= 1.5f * s.s_max[k]);
-        bool g2 = (l == s.n_levels - 1) || (S >= 0.5f * s.s_min[k]) || (S >= 2.0f);
+        bool g1 = (l == 0) || (S <= 1.5f * smax);
+        bool g2 = (l == s.n_levels - 1) || (S >= 0.5f * smin) || (S >= 2.0f);
         sel = g1 && g2;
       }
       if (l == v.update_level) {
         // range update after the selection test has read the old values
-        s.s_max[k] = fmaxf(0.95f * s.s_max[k], S);
-        s.s_min[k] = fminf(1.05f * s.s_min[k], S);
+        s.s_max[k] = fmaxf(0.95f * smax, S);
+        s.s_min[k] = fminf(1.05f * smin, S);
       }
     }
     selected = sel ? 1 : 0;
@@ -115,7 +126,6 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, u
         if (xh >= xl && yh >= yl) {
           ntiles = (uint32_t)(xh - xl + 1) * (uint32_t)(yh - yl + 1);
           // colour towards the camera centre
-          float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
           float d0 = mu0 - v.C[0], d1 = mu1 - v.C[1], d2 = mu2 - v.C[2];
           float dn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
           d0 = d0 / dn;

@@ -206,9 +206,8 @@ struct Geo {
 
 // The part of the geometry that does not depend on the view: normalised
 // quaternion, its rotation, scales and the 3D covariance Sigma = M M^T.
-__device__ __forceinline__ void geo_shape(const SceneView& s, int64_t k, Geo& g) {
-  const int64_t n = s.n;
-  float qw = s.quats[k], qx = s.quats[n + k], qy = s.quats[2 * n + k], qz = s.quats[3 * n + k];
+__device__ __forceinline__ void geo_shape_of(float qw, float qx, float qy, float qz, float s0,
+                                             float s1, float s2, Geo& g) {
   float nrm2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
   float r = sqrtf(nrm2);
   g.qlen = r;
@@ -217,9 +216,9 @@ __device__ __forceinline__ void geo_shape(const SceneView& s, int64_t k, Geo& g)
   g.qn[2] = qy / r;
   g.qn[3] = qz / r;
   quat_rot(g.qn[0], g.qn[1], g.qn[2], g.qn[3], g.Q);
-  g.sc[0] = s.scales[k];
-  g.sc[1] = s.scales[n + k];
-  g.sc[2] = s.scales[2 * n + k];
+  g.sc[0] = s0;
+  g.sc[1] = s1;
+  g.sc[2] = s2;
   float M[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -235,6 +234,12 @@ __device__ __forceinline__ void geo_shape(const SceneView& s, int64_t k, Geo& g)
     }
   g.Sg[0] = S[0][0]; g.Sg[1] = S[0][1]; g.Sg[2] = S[0][2];
   g.Sg[3] = S[1][1]; g.Sg[4] = S[1][2]; g.Sg[5] = S[2][2];
+}
+
+__device__ __forceinline__ void geo_shape(const SceneView& s, int64_t k, Geo& g) {
+  const int64_t n = s.n;
+  geo_shape_of(s.quats[k], s.quats[n + k], s.quats[2 * n + k], s.quats[3 * n + k], s.scales[k],
+               s.scales[n + k], s.scales[2 * n + k], g);
 }
 
 // The view-dependent part, given geo_shape's fields and the mean mu.
