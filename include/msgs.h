@@ -222,8 +222,8 @@ int msgs_render_backward(msgs_context* ctx, const msgs_frame* frame, const float
  *   frames   host array of nviews frames of the same scene and context
  *   dL_drgb  host array of nviews device pointers, [H_d][W_d][3] fp32 each
  *   nviews   >= 1 (else MSGS_E_INVALID)
- * Temporary device memory: 48 bytes per Gaussian per view plus 52 bytes per
- * tile instance of the largest frame. */
+ * Temporary device memory: 48 bytes per Gaussian per view, 4 per Gaussian,
+ * and 36 bytes plus one bit per tile instance of the largest frame. */
 int msgs_render_backward_views(msgs_context* ctx, const msgs_frame* const* frames,
                                const float* const* dL_drgb, int nviews, const msgs_grads* out,
                                void* stream);

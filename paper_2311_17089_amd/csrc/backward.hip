@@ -15,8 +15,8 @@
 //                contiguous emission range, in slot order.  Threads walk the
 //                Gaussians in emission (depth) order so that a wave reads one
 //                contiguous span; a Gaussian with more than 64 tiles gets a
-//                workgroup.  Partials and
-//                sums are stored as three float4 per instance / Gaussian.
+//                workgroup.  Partials are nine floats (36 bytes) per
+//                instance, sums three float4 per Gaussian.
 //  k_chain       chain rule per Gaussian from (u, conic, sigma, colour) to the
 //                scene parameters (means, linear scales, raw quaternion,
 //                opacity, SH), recomputing the projection of the forward.
@@ -259,10 +259,10 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
         any = any || r != 0.0f;
       }
       if (any) {
-        float4* P = (float4*)partial + (int64_t)slot * 3;
-        P[0] = make_float4(sm[0], sm[1], sm[2], sm[3]);
-        P[1] = make_float4(sm[4], sm[5], sm[6], sm[7]);
-        P[2] = make_float4(sm[8], 0.0f, 0.0f, 0.0f);
+        float3* P = (float3*)(partial + (int64_t)slot * kNP);
+        P[0] = make_float3(sm[0], sm[1], sm[2]);
+        P[1] = make_float3(sm[3], sm[4], sm[5]);
+        P[2] = make_float3(sm[6], sm[7], sm[8]);
         atomicOr(&wmask[slot >> 5], 1u << (slot & 31u));
       }
     }
@@ -271,11 +271,13 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
   }
 }
 
-__device__ __forceinline__ void acc3(float* s, const float4* P) {
-  const float4 a = P[0], b = P[1], c = P[2];
-  s[0] += a.x; s[1] += a.y; s[2] += a.z; s[3] += a.w;
-  s[4] += b.x; s[5] += b.y; s[6] += b.z; s[7] += b.w;
-  s[8] += c.x;
+// s += the nine partials of one slot (three float3, 36 bytes)
+__device__ __forceinline__ void acc9(float* s, const float* partial, int64_t slot) {
+  const float3* P = (const float3*)(partial + slot * kNP);
+  const float3 a = P[0], b = P[1], c = P[2];
+  s[0] += a.x; s[1] += a.y; s[2] += a.z;
+  s[3] += b.x; s[4] += b.y; s[5] += b.z;
+  s[6] += c.x; s[7] += c.y; s[8] += c.z;
 }
 
 __device__ __forceinline__ void store3(float* gsum, int64_t k, const float* s) {
@@ -308,7 +310,6 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
   for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
   // only the slots whose partial was written (bit set) are read, in order
   const uint32_t e0 = min(emit_base[k], cap), e1 = min(emit_base[k] + c, cap);
-  const float4* P = (const float4*)partial;
   for (uint32_t w0 = e0 & ~31u; w0 < e1; w0 += 32u) {
     uint32_t bits = wmask[w0 >> 5];
     const uint32_t lo = e0 > w0 ? e0 - w0 : 0u;
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
     while (bits) {
       const uint32_t b = (uint32_t)__ffs(bits) - 1u;
       bits &= bits - 1u;
-      acc3(s, P + 3 * (int64_t)(w0 + b));
+      acc9(s, partial, (int64_t)(w0 + b));
     }
   }
   store3(gsum, k, s);
@@ -335,13 +336,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
     const uint32_t k = big[i];
     const uint32_t e0 = min(emit_base[k], cap);
     const uint32_t c = min(emit_base[k] + count[k], cap) - e0;
-    const float4* P = (const float4*)partial;
     float s[kNP];
 #pragma unroll
     for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
     for (uint32_t t = threadIdx.x; t < c; t += kBlock) {
       const uint32_t e = e0 + t;
-      if ((wmask[e >> 5] >> (e & 31u)) & 1u) acc3(s, P + 3 * (int64_t)e);
+      if ((wmask[e >> 5] >> (e & 31u)) & 1u) acc9(s, partial, (int64_t)e);
     }
 #pragma unroll
     for (int q = 0; q < kNP; ++q) {

@@ -599,7 +599,7 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   a.g_sh = out->sh;
   a.accumulate = out->accumulate ? 1 : 0;
   Carve tmp;
-  tmp.add(&a.partial, (size_t)48 * (size_t)f->n_inst);
+  tmp.add(&a.partial, (size_t)36 * (size_t)f->n_inst);
   tmp.add((void**)&a.wmask, (size_t)4 * (size_t)((f->n_inst + 31) / 32));
   tmp.add(&a.gsum, (size_t)48 * (size_t)n);
   tmp.add(&a.big, (size_t)4 * (size_t)n);
@@ -651,7 +651,7 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
   uint32_t* big = nullptr;
   uint32_t* nbig = nullptr;
   Carve tmp;
-  tmp.add((void**)&partial, (size_t)48 * (size_t)max_inst);
+  tmp.add((void**)&partial, (size_t)36 * (size_t)max_inst);
   tmp.add((void**)&wmask, (size_t)4 * (size_t)((max_inst + 31) / 32));
   tmp.add((void**)&gsum, (size_t)48 * (size_t)n * (size_t)nviews);
   tmp.add((void**)&big, (size_t)4 * (size_t)n);

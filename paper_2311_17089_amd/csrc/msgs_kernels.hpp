@@ -80,7 +80,7 @@ struct BwdArgs {
   const float* T_final;
   const uint32_t* n_last;
   const float* dL_drgb;
-  float* partial;           // [n_inst][12] per-instance partials (9 used), written where nonzero
+  float* partial;           // [n_inst][9] per-instance partials, written where nonzero
   uint32_t* wmask;          // [ceil(n_inst/32)] bit per instance: its partial was written
   int64_t n_inst;
   float* gsum;              // [n][12] per-Gaussian sums (9 used)
