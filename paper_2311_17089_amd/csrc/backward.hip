@@ -140,7 +140,11 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
     d1 = dLdC[pix * 3 + 1];
     d2 = dLdC[pix * 3 + 2];
   }
-  float B0 = T * v.bg[0], B1 = T * v.bg[1], B2 = T * v.bg[2];
+  // the suffix colour B (contributions behind the current entry plus the
+  // background seen through them) enters the adjoint only through d . B, so
+  // the replay carries that one scalar: dB = d . (T_final bg) at the start,
+  // dB += (d . c) w after each entry
+  float dB = T * ((d0 * v.bg[0] + d1 * v.bg[1]) + d2 * v.bg[2]);
   // largest contributor count in the tile
   uint32_t wm = last;
 #pragma unroll
@@ -216,17 +220,16 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       const float om = __builtin_amdgcn_rcpf(1.0f - al);
       const float Tb = T * om;
       // lanes that do not contribute get w = 0 and dar = 0, which zero all
-      // nine partials and leave B unchanged
+      // nine partials and leave dB unchanged
       const float w = contrib ? al * Tb : 0.0f;
       float g[kNP];
       g[6] = d0 * w;
       g[7] = d1 * w;
       g[8] = d2 * w;
-      const float dal = d0 * (c0 * Tb - B0 * om) + d1 * (c1 * Tb - B1 * om) +
-                        d2 * (c2 * Tb - B2 * om);
-      B0 = B0 + c0 * w;
-      B1 = B1 + c1 * w;
-      B2 = B2 + c2 * w;
+      // dL/dalpha = T_j (d . c) - (d . B) / (1 - alpha)
+      const float dc = fmaf(d2, c2, fmaf(d1, c1, d0 * c0));
+      const float dal = fmaf(Tb, dc, -(om * dB));
+      dB = fmaf(dc, w, dB);
       T = contrib ? Tb : T;
       const float dar = (ar > kAlphaMax || !contrib) ? 0.0f : dal;
       g[5] = dar * ex;
@@ -234,8 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       g[2] = dp * (-0.5f * qxx);
       g[3] = dp * (-qxy);
       g[4] = dp * (-0.5f * qyy);
-      g[0] = dp * (a.z * dx + a.w * dy);
-      g[1] = dp * (b.x * dy + a.w * dx);
+      g[0] = dp * fmaf(a.z, dx, a.w * dy);
+      g[1] = dp * fmaf(b.x, dy, a.w * dx);
       if (__ballot(contrib)) {
         const float tot = wave_reduce9(g, lane);
         const int q = slot_q(lane & 15);

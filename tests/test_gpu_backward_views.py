@@ -106,6 +106,19 @@ def test_views_reject_mixed_scenes(ctx):
         M.render_backward_views(ctx, fa + fb, da + db, grads=None)
     with pytest.raises(ValueError):
         M.render_backward_views(ctx, [], [])
+    # the C entry point itself: no views, and a frame of another context
+    g = {k: torch.empty_like(a.t[k]) for k in NAMES}
+    gs = M.Grads(*[g[k].data_ptr() for k in NAMES], 0)
+    L = M.lib()
+    fr_arr = (M.C.c_void_p * 1)(fa[0].h)
+    dl_arr = (M.C.c_void_p * 1)(da[0].data_ptr())
+    assert L.msgs_render_backward_views(ctx.h, fr_arr, dl_arr, 0, M.C.byref(gs), None) == \
+        M.E_INVALID
+    other = M.Context(0)
+    assert L.msgs_render_backward_views(other.h, fr_arr, dl_arr, 1, M.C.byref(gs), None) == \
+        M.E_INVALID
+    assert L.msgs_render_backward_views(ctx.h, fr_arr, dl_arr, 1, M.C.byref(gs), None) == M.OK
+    torch.cuda.synchronize()
     for fr in fa + fb:
         fr.release()
     a.close()
