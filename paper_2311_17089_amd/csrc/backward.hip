@@ -3,10 +3,11 @@
 //  k_blend_bwd   one workgroup per tile (XCD-aware order, as the forward).
 //                Each pixel replays its contributors back to front from the
 //                stored final transmittance (T_j = T_{j+1} / (1 - alpha_j)) and
-//                the suffix colour B_j; the nine partial derivatives of every
-//                instance (d u, d conic, d sigma, d colour) are summed over the
-//                tile's 256 pixels by DPP wave reductions and a four-wave LDS
-//                sum, and written once to the instance's emission slot, with
+//                the suffix colour B_j; nine sums per instance (d sigma, d
+//                colour, and the moments of dL/dsigma over the pixel offsets,
+//                from which d u and d conic follow) are taken over the tile's
+//                256 pixels by DPP wave reductions and a four-wave LDS sum,
+//                and the partials written once to the instance's emission slot, with
 //                its bit set in a per-instance mask (most instances contribute
 //                to no pixel, so their partials are neither cleared nor read).
 //                The sums themselves use no atomics: the result is
@@ -231,14 +232,19 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       const float dal = fmaf(Tb, dc, -(om * dB));
       dB = fmaf(dc, w, dB);
       T = contrib ? Tb : T;
+      // h = dL/dsigma of this pixel, and dL/dpower = sigma h: the partials of
+      // the centre and the conic are summed as the moments of h over the
+      // pixel offsets (h dx, h dy, h dx^2, h dx dy, h dy^2) and turned into
+      // them once per instance after the sums
       const float dar = (ar > kAlphaMax || !contrib) ? 0.0f : dal;
-      g[5] = dar * ex;
-      const float dp = dar * ar;
-      g[2] = dp * (-0.5f * qxx);
-      g[3] = dp * (-qxy);
-      g[4] = dp * (-0.5f * qyy);
-      g[0] = dp * fmaf(a.z, dx, a.w * dy);
-      g[1] = dp * fmaf(b.x, dy, a.w * dx);
+      const float h = dar * ex;
+      const float hx = h * dx, hy = h * dy;
+      g[0] = hx;
+      g[1] = hy;
+      g[2] = hx * dx;
+      g[3] = hx * dy;
+      g[4] = hy * dy;
+      g[5] = h;
       if (__ballot(contrib)) {
         const float tot = wave_reduce9(g, lane);
         const int q = slot_q(lane & 15);
@@ -262,9 +268,15 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
         any = any || r != 0.0f;
       }
       if (any) {
+        // moments -> d u and d conic: power = -(A11 dx^2 + A22 dy^2)/2 - A12 dx dy
+        // with dx = x - u_x, so dpower/du_x = A11 dx + A12 dy and so on
+        const float4 ra = s0[threadIdx.x], rb = s1[threadIdx.x];
+        const float sg = rb.y;
+        const float mx = sm[0], my = sm[1];
         float3* P = (float3*)(partial + (int64_t)slot * kNP);
-        P[0] = make_float3(sm[0], sm[1], sm[2]);
-        P[1] = make_float3(sm[3], sm[4], sm[5]);
+        P[0] = make_float3(sg * fmaf(ra.z, mx, ra.w * my), sg * fmaf(rb.x, my, ra.w * mx),
+                           -0.5f * sg * sm[2]);
+        P[1] = make_float3(-sg * sm[3], -0.5f * sg * sm[4], sm[5]);
         P[2] = make_float3(sm[6], sm[7], sm[8]);
         atomicOr(&wmask[slot >> 5], 1u << (slot & 31u));
       }
