@@ -2,8 +2,9 @@
 //
 //  k_blend_bwd   one workgroup per tile (XCD-aware order, as the forward).
 //                Each pixel replays its contributors back to front from the
-//                stored final transmittance (T_j = T_{j+1} / (1 - alpha_j)) and
-//                the suffix colour B_j; nine sums per instance (d sigma, d
+//                stored final transmittance (T_j = T_{j+1} / (1 - alpha_j)),
+//                carrying d . B_j (its dL/dC with the suffix colour B_j, the
+//                only form in which B enters); nine sums per instance (d sigma, d
 //                colour, and the moments of dL/dsigma over the pixel offsets,
 //                from which d u and d conic follow) are taken over the tile's
 //                256 pixels by DPP wave reductions and a four-wave LDS sum,
@@ -21,6 +22,8 @@
 //  k_chain       chain rule per Gaussian from (u, conic, sigma, colour) to the
 //                scene parameters (means, linear scales, raw quaternion,
 //                opacity, SH), recomputing the projection of the forward.
+//  k_chain_views the chain rule of up to eight views in one pass (parameters
+//                read and gradients written once per Gaussian).
 #include <algorithm>
 
 #include "msgs_device.hpp"

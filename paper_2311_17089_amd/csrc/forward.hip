@@ -12,12 +12,12 @@
 //              row-major, Gaussians in depth order (each wave writes its
 //              Gaussians' contiguous stretch of the list, 64 at a time).
 //  k_ranges    half-open range of every tile in the tile-sorted list.
-//  k_blend     one 256-thread workgroup per 16x16 tile whose four wave64s
-//              work independently on their 8x8 quadrants: per 64-instance chunk
-//              a ballot keeps the instances whose level-set box reaches the
-//              quadrant, packed in order into the wave's LDS buffer; branch-free
-//              front-to-back compositing with per-wave early exit; the next
-//              chunk's gathers in flight meanwhile; XCD-aware tile order.
+//  k_blend     one single-wave workgroup per 8x8 quadrant of a 16x16 tile:
+//              per 64-instance chunk of the tile's list a ballot keeps the
+//              instances whose level set can reach the quadrant, packed in
+//              order into the wave's LDS buffer; branch-free front-to-back
+//              compositing, four instances per step, with early exit; the next
+//              chunk's gathers in flight meanwhile; XCD-aware quadrant order.
 #include <algorithm>
 
 #include "msgs_device.hpp"
