@@ -67,30 +67,32 @@ __device__ __forceinline__ int slot_q(int lane) { return (int)((kSlotTable >> (4
 
 __device__ __forceinline__ float wave_reduce9(const float (&v)[9], int lane) {
   const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0, b0 = (lane & 1) != 0;
+  // A stage pairs value k with value k + m; where k + m does not exist, the
+  // lanes that would keep it end in a slot no value maps to (kSlotTable), so
+  // both sides just add their own value k and no select is needed there.
   float a[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    const float hi = k < 4 ? v[5 + k] : 0.0f;
-    const float keep = b3 ? hi : v[k];
-    const float send = b3 ? v[k] : hi;
+  for (int k = 0; k < 4; ++k) {
+    const float keep = b3 ? v[5 + k] : v[k];
+    const float send = b3 ? v[k] : v[5 + k];
     a[k] = keep + MSGS_DPP(send, 0x128);  // row_ror:8 (lane ^ 8 within the row)
   }
+  a[4] = v[4] + MSGS_DPP(v[4], 0x128);
   float c[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const float hi = k < 2 ? a[3 + k] : 0.0f;
-    const float keep = b2 ? hi : a[k];
-    const float send = b2 ? a[k] : hi;
+  for (int k = 0; k < 2; ++k) {
+    const float keep = b2 ? a[3 + k] : a[k];
+    const float send = b2 ? a[k] : a[3 + k];
     c[k] = keep + MSGS_DPP(send, 0x141);  // row_half_mirror (flips bit 2)
   }
+  c[2] = a[2] + MSGS_DPP(a[2], 0x141);
   float d[2];
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const float hi = k == 0 ? c[2] : 0.0f;
-    const float keep = b1 ? hi : c[k];
-    const float send = b1 ? c[k] : hi;
-    d[k] = keep + MSGS_DPP(send, 0x4E);  // quad_perm [2,3,0,1]
+  {
+    const float keep = b1 ? c[2] : c[0];
+    const float send = b1 ? c[0] : c[2];
+    d[0] = keep + MSGS_DPP(send, 0x4E);  // quad_perm [2,3,0,1]
   }
+  d[1] = c[1] + MSGS_DPP(c[1], 0x4E);
   const float keep = b0 ? d[1] : d[0];
   const float send = b0 ? d[0] : d[1];
   float e = keep + MSGS_DPP(send, 0xB1);  // quad_perm [1,0,3,2]
@@ -210,11 +212,11 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       const float qxx = dx * dx, qyy = dy * dy, qxy = dx * dy;
       const float e = -0.5f * (a.z * qxx + b.x * qyy);
       const float power = e - a.w * qxy;
-      // exp of a power clamped at -100: the entries that contribute have
-      // power >= -(lnq + 2^-8) > -6 and see the forward's value; for the rest
-      // it stays finite (a Gaussian centre far outside the image makes the
-      // power of order -1e12), so that the zero factors below give zeros
-      const float ex = exp_c(fmaxf(power, -100.0f));
+      // exp of the power clamped to [-100, 0]: the entries that contribute
+      // have -(lnq + 2^-8) <= power <= 0 and see the forward's value; for the
+      // rest it stays finite (a Gaussian centre far outside the image makes
+      // the power of order -1e12), so that the zero factors below give zeros
+      const float ex = exp_c(__builtin_amdgcn_fmed3f(power, -100.0f, 0.0f));
       const float ar = b.y * ex;
       const bool contrib = pos < last && !(power > 0.0f || power < b.z) && !(ar < kAlphaMin);
       const float c0 = b.w, c1 = c.x, c2 = c.y;
