@@ -234,14 +234,17 @@ __global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* keys, const
                                                      int64_t nmax, int shift, int nbits,
                                                      uint32_t* counts, int64_t nblk) {
   constexpr int TILE = kBlock * ITEMS;
-  __shared__ uint32_t h[kBlock / 64][kRadix];
-  const int wave = threadIdx.x >> 6;
+  // one sub-histogram per (wave, lane mod 4): keys of neighbouring instances
+  // often share a digit, and a shared LDS counter serialises its atomics
+  constexpr int kSub = kBlock / 16;
+  __shared__ uint32_t h[kSub][kRadix];
+  const int sub = ((threadIdx.x >> 6) << 2) | (threadIdx.x & 3);
   const int64_t n = d_n ? (int64_t)*d_n : nmax;
   const int64_t t = blockIdx.x;
   const int64_t tbase = t * TILE;
   if (tbase >= n) return;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) h[w][threadIdx.x] = 0;
+  for (int w = 0; w < kSub; ++w) h[w][threadIdx.x] = 0;
   __syncthreads();
   const uint32_t mask = (1u << nbits) - 1u;
   uint32_t k_[ITEMS];
@@ -252,11 +255,11 @@ __global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* keys, const
   }
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i)
-    if (tbase + i * kBlock + threadIdx.x < n) atomicAdd(&h[wave][(k_[i] >> shift) & mask], 1u);
+    if (tbase + i * kBlock + threadIdx.x < n) atomicAdd(&h[sub][(k_[i] >> shift) & mask], 1u);
   __syncthreads();
   uint32_t c = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) c += h[w][threadIdx.x];
+  for (int w = 0; w < kSub; ++w) c += h[w][threadIdx.x];
   counts[(int64_t)threadIdx.x * nblk + t] = c;
 }
 
