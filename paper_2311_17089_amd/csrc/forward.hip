@@ -387,9 +387,11 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
         const bool stop = ok && Tn < kTMin;
         const bool acc = ok && !stop;
         const float w = acc ? al * T : 0.0f;
-        C0 = C0 + cb[u].x * w;
-        C1 = C1 + cb[u].y * w;
-        C2 = C2 + cb[u].z * w;
+        // colour is not a decision: fused (within one rounding of the
+        // unfused sum; transmittance and every test stay unfused)
+        C0 = fmaf(cb[u].x, w, C0);
+        C1 = fmaf(cb[u].y, w, C1);
+        C2 = fmaf(cb[u].z, w, C2);
         T = acc ? Tn : T;
         cnt += acc ? 1u : 0u;
         last = acc ? p1[u] : last;
