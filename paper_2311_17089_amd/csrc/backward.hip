@@ -335,10 +335,38 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
     const uint32_t lo = e0 > w0 ? e0 - w0 : 0u;
     const uint32_t hi = e1 - w0 >= 32u ? 32u : e1 - w0;
     bits &= (hi == 32u ? ~0u : ((1u << hi) - 1u)) & (~0u << lo);
+    // up to four written slots per round: their loads are all issued before
+    // the first sum needs one, and the sums still run in slot order
     while (bits) {
-      const uint32_t b = (uint32_t)__ffs(bits) - 1u;
-      bits &= bits - 1u;
-      acc9(s, partial, (int64_t)(w0 + b));
+      uint32_t e[4];
+      int m = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        e[u] = w0;
+        if (bits) {
+          e[u] = w0 + (uint32_t)__ffs(bits) - 1u;
+          bits &= bits - 1u;
+          m = u + 1;
+        }
+      }
+      float3 P[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u < m) {
+          const float3* p = (const float3*)(partial + (int64_t)e[u] * kNP);
+          P[u][0] = p[0];
+          P[u][1] = p[1];
+          P[u][2] = p[2];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (u < m) {
+          s[0] += P[u][0].x; s[1] += P[u][0].y; s[2] += P[u][0].z;
+          s[3] += P[u][1].x; s[4] += P[u][1].y; s[5] += P[u][1].z;
+          s[6] += P[u][2].x; s[7] += P[u][2].y; s[8] += P[u][2].z;
+        }
+      }
     }
   }
   store3(gsum, k, s);
