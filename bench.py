@@ -8,7 +8,12 @@ established by the library's own range update over 8 seeded cameras, one
 the four downscales 1x, 4x, 16x, 64x with selective rendering: forward render
 (projection, coverage, selection, SH, binning, sorts, blending) and the
 backward pass against a fixed seeded dL/dRGB.  Inputs are resident in HBM
-before timing; the timed region is bracketed by device synchronisation.
+before timing; the timed region is bracketed by device synchronisation.  The
+timed steps replay one captured HIP graph per frame (fixed tile-list capacity
+of 1.25x the counted instances, so no host synchronisation inside a frame),
+the four frames on four streams; every replayed frame is checked to have done
+the counted work.  The eager step (exact tile lists, one host thread and
+stream per frame) is timed too and reported beside it.
 
 Metric: Gaussian-pixel blends per second (accumulated contributions of the
 forward renders of one step, divided by the step time).  The JSON line also
@@ -31,7 +36,7 @@ DOWNSCALES = (1, 4, 16, 64)
 W_FULL, H_FULL, FOCAL = 1600, 1064, 1875.0
 HBM_PEAK_GBS = 8000.0
 # fp32 vector rate without packed math: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
-# x 2 flops per fma (packed fp32 is disabled in this build).
+# x 2 flops per fma (the library is compiled with packed fp32 disabled).
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 # algorithmic fp32 flops of the compositing loop (fma = 2): every evaluated
 # (pixel, instance) pair costs the offset and quadratic form (11); every
@@ -374,10 +379,13 @@ def main():
                     help="run one serial step and a 1 GiB elementwise copy, for HBM counter runs")
     ap.add_argument("--serial", action="store_true",
                     help="render the frames of a step one after another on one stream")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager steps (exact tile lists, one host thread per frame) instead "
+                         "of the replayed per-frame HIP graphs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the hot path runs on a single MI355X and this build "
-              "has no multi-GPU path (see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: the hot path runs on a single MI355X and the library "
+              "has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -406,8 +414,14 @@ def main():
     # on the frame's stream, accumulated over the kernel-timing steps
     stage_acc = {ds: {s: 0.0 for s in STAGES} for ds in DOWNSCALES}
 
-    def run_frame(ds, st=None, prof=False):
-        _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, profile=prof, stream=st)
+    # fixed tile-list capacities (set after the counting step) for the frames
+    # that run without a host synchronisation: eager capacity-mode warm-up
+    # and the captured graphs
+    caps = {}
+
+    def run_frame(ds, st=None, prof=False, capacity=False):
+        _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, profile=prof, stream=st,
+                         capacity=caps[ds] if capacity else 0)
         M.render_backward(ctx, fr, dls[ds], stream=st)
         if prof:
             us = fr.stats()["stage_us"]  # waits for this frame's stream
@@ -415,18 +429,31 @@ def main():
                 stage_acc[ds][s] += us[STAGE_IDX[s]]
         fr.release()
 
-    def frame(ds):
+    def frame(ds, capacity=False):
         st = streams[ds]
         with torch.cuda.stream(st):
-            run_frame(ds, st)
+            run_frame(ds, st, capacity=capacity)
 
-    def step(prof=False):
+    def eager_step(prof=False, capacity=False):
         if args.serial or prof:
             for ds in DOWNSCALES:
                 run_frame(ds, prof=prof)
             return
-        for f in [pool.submit(frame, ds) for ds in DOWNSCALES]:
+        for f in [pool.submit(frame, ds, capacity) for ds in DOWNSCALES]:
             f.result()
+
+    graphs = {}
+
+    def step(prof=False):
+        if prof or not graphs:
+            eager_step(prof=prof)
+            return
+        # one host thread replays the four frames' graphs, each on its stream
+        cur = torch.cuda.current_stream()
+        for ds in DOWNSCALES:
+            streams[ds].wait_stream(cur)
+            with torch.cuda.stream(streams[ds]):
+                graphs[ds].replay()
 
     # counts of one step (deterministic)
     stats = {}
@@ -436,6 +463,8 @@ def main():
         stats[ds] = fr.stats()
         fr.release()
     blends_per_step = sum(stats[ds]["n_blends"] for ds in DOWNSCALES)
+    for ds in DOWNSCALES:
+        caps[ds] = int(stats[ds]["n_instances"] * 1.25) + 4096
 
     if args.traffic_probe:
         # the counters of this run give the HBM bytes of every kernel of one
@@ -455,13 +484,47 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    print("bench: timed steps", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
+
+    def timed():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps * 1e3
+
+    print("bench: timed eager steps", file=sys.stderr, flush=True)
+    ms_eager = timed()
+    graph_frames = {}
+    if not (args.eager or args.serial):
+        # capture: eager capacity-mode frames on every stream first, so that
+        # the library's block cache holds each stream's blocks, then one graph
+        # per frame (forward + backward) on the frame's stream
+        print("bench: capturing one graph per frame", file=sys.stderr, flush=True)
+        for _ in range(2):
+            eager_step(capacity=True)
+        torch.cuda.synchronize()
+        for ds in DOWNSCALES:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=streams[ds]):
+                _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, stream=streams[ds],
+                                 capacity=caps[ds])
+                gr = M.render_backward(ctx, fr, dls[ds], stream=streams[ds])
+            graphs[ds] = g
+            graph_frames[ds] = (fr, gr)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        for ds in DOWNSCALES:
+            # a replayed frame did the counted work (and did not overflow)
+            gs = graph_frames[ds][0].stats()
+            for k in ("n_selected", "n_instances", "n_blends", "n_visits"):
+                assert gs[k] == stats[ds][k], (ds, k, gs[k], stats[ds][k])
+        print("bench: timed graph replays", file=sys.stderr, flush=True)
+        ms_per_step = timed()
+    else:
+        ms_per_step = ms_eager
     pool.shutdown()
     # kernel timing: the same steps with the frames one after another, so that
     # a kernel's launch time is its own and not shared with another frame's
@@ -570,7 +633,14 @@ def main():
                                "per downscale",
                    "n_gaussians": sc.n, "frames_per_step": len(DOWNSCALES),
                    "frames_in_flight": 1 if args.serial else len(DOWNSCALES),
-                   "blends_per_step": blends_per_step},
+                   "blends_per_step": blends_per_step,
+                   "execution": ("eager, frames one after another on one stream" if args.serial
+                                 else "eager, one host thread and stream per frame, exact tile "
+                                      "lists" if (args.eager or not graphs)
+                                 else "one captured HIP graph per frame (forward + backward, "
+                                      "tile-list capacity 1.25x the counted instances + 4096), "
+                                      "the four replayed on four streams")},
+        "ms_per_step_eager": ms_eager,
         "roofline": roof,
         "stage_us_per_step": {s: round(v, 2) for s, v in stage_tot.items()},
         "hbm_stages": hbm_stages,
@@ -593,6 +663,10 @@ def main():
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+    graphs.clear()
+    torch.cuda.synchronize()
+    for fr, _ in graph_frames.values():
+        fr.release()
     dsc.close()
     del stream
 

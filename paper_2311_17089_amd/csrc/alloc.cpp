@@ -85,6 +85,14 @@ void DeviceCache::release_idle() {
 
 int DeviceCache::alloc(msgs_context* c, void** out, size_t bytes, hipStream_t st) {
   const size_t sz = round_size(bytes);
+  // under stream capture an event query would invalidate the capture: only a
+  // block freed on the capturing stream itself is taken then
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) {
+    (void)hipGetLastError();
+    cap = hipStreamCaptureStatusNone;
+  }
+  const bool capturing = cap != hipStreamCaptureStatusNone;
   {
     std::lock_guard<std::mutex> g(impl->mu);
     if (c->budget && c->in_use.load() + sz > c->budget)
@@ -99,7 +107,8 @@ int DeviceCache::alloc(msgs_context* c, void** out, size_t bytes, hipStream_t st
         pick = it;
         break;
       }
-      if (pick == impl->free_.end() && it->second.ev && hipEventQuery(it->second.ev) == hipSuccess)
+      if (!capturing && pick == impl->free_.end() && it->second.ev &&
+          hipEventQuery(it->second.ev) == hipSuccess)
         pick = it;
     }
     if (pick != impl->free_.end()) {

@@ -2,7 +2,8 @@
 an MI355X).  A fixed tile-instance capacity removes the render's only host
 synchronisation, so forward and backward can be captured; results must equal
 the exact mode bit for bit, overflow must be reported, and every replay of the
-captured step must reproduce the eager step."""
+captured step must reproduce the eager step, also with one graph per frame
+captured on several streams and replayed concurrently."""
 import numpy as np
 import pytest
 import torch
@@ -143,6 +144,83 @@ def test_captured_training_step_replays_exactly(views_backward):
         o2.close()
     _say(f"  captured {len(views)} views, 3 replays identical to the eager step")
     del g
+    torch.cuda.synchronize()
+    for fr in frames:
+        fr.release()
+    dsc.close()
+
+
+def test_frames_captured_on_several_streams():
+    """One graph per frame, each captured on its own stream while the
+    library's block cache also holds blocks freed on the other streams (the
+    cache must then take only the capturing stream's blocks: an event query
+    would invalidate the capture); the graphs replayed concurrently must
+    reproduce the eager frames bit for bit."""
+    _say("  frames captured on three streams")
+    ctx = M.Context(0)
+    dsc = _scene(ctx)
+    views = _views()[:3]
+    dls = [torch.randn((240 // d, 320 // d, 3), generator=torch.Generator().manual_seed(30 + i))
+           .cuda() * 1e-3 for i, (_, d) in enumerate(views)]
+    caps = []
+    for cam, d in views:
+        _, fr = M.render(ctx, dsc, cam, downscale=d, keep_frame=True)
+        caps.append(int(fr.stats()["n_instances"] * 1.25) + 64)
+        fr.release()
+    outs = [torch.empty((240 // d, 320 // d, 3), device="cuda") for _, d in views]
+    grads = [{k: torch.empty_like(dsc.t[k]) for k in NAMES} for _ in views]
+    streams = [torch.cuda.Stream() for _ in views]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+
+    def frame(i, keep=False):
+        cam, d = views[i]
+        _, fr = M.render(ctx, dsc, cam, downscale=d, keep_frame=True, capacity=caps[i],
+                         out=outs[i], stream=streams[i])
+        M.render_backward(ctx, fr, dls[i], stream=streams[i], grads=grads[i])
+        if keep:
+            return fr
+        fr.release()
+        return None
+
+    # eager runs on every stream leave freed blocks of all three in the cache
+    for _ in range(2):
+        for i in range(len(views)):
+            with torch.cuda.stream(streams[i]):
+                frame(i)
+    torch.cuda.synchronize()
+    for i in range(len(views)):
+        with torch.cuda.stream(streams[i]):
+            frame(i)
+    torch.cuda.synchronize()
+    ref_img = [o.cpu().numpy() for o in outs]
+    ref_g = [{k: v.cpu().numpy() for k, v in g.items()} for g in grads]
+
+    graphs, frames = [], []
+    for i in range(len(views)):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=streams[i]):
+            frames.append(frame(i, keep=True))
+        graphs.append(g)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for i in range(len(views)):
+            outs[i].fill_(-1.0)
+            for k in NAMES:
+                grads[i][k].fill_(7.0)
+        torch.cuda.synchronize()
+        for i in range(len(views)):
+            streams[i].wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(streams[i]):
+                graphs[i].replay()
+        torch.cuda.synchronize()
+        for i in range(len(views)):
+            np.testing.assert_array_equal(outs[i].cpu().numpy(), ref_img[i])
+            for k in NAMES:
+                np.testing.assert_array_equal(grads[i][k].cpu().numpy(), ref_g[i][k])
+            frames[i].stats()  # no overflow
+    _say("  2 concurrent replays identical to the eager frames")
+    del graphs
     torch.cuda.synchronize()
     for fr in frames:
         fr.release()
