@@ -497,14 +497,17 @@ def main():
     ms_eager = timed()
     graph_frames = {}
     if not (args.eager or args.serial):
-        # capture: eager capacity-mode frames on every stream first, so that
-        # the library's block cache holds each stream's blocks, then one graph
-        # per frame (forward + backward) on the frame's stream
+        # capture: one graph per frame (forward + backward) on the frame's
+        # stream, each right after an eager capacity-mode frame on that stream,
+        # whose freed blocks the captured frame then takes from the library's
+        # block cache
         print("bench: capturing one graph per frame", file=sys.stderr, flush=True)
         for _ in range(2):
             eager_step(capacity=True)
         torch.cuda.synchronize()
         for ds in DOWNSCALES:
+            with torch.cuda.stream(streams[ds]):
+                run_frame(ds, streams[ds], capacity=True)
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=streams[ds]):
                 _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, stream=streams[ds],

@@ -119,12 +119,17 @@ typedef struct {
   long long instance_capacity; /* 0: exact mode, the tile-instance count is read
                         back once per render (one host synchronisation) to
                         size the tile lists.  > 0: fixed capacity, no host
-                        synchronisation and no allocation beyond the cached
-                        ones, so that the render (and its backward) can be
-                        captured in a HIP graph; if the frame needs more
-                        instances its image is incomplete and
-                        msgs_frame_stats returns MSGS_E_CAPACITY.  Not with
-                        profile = 1. */
+                        synchronisation, so that the render (and its
+                        backward) can be captured in a HIP graph; if the
+                        frame needs more instances its image is incomplete
+                        and msgs_frame_stats returns MSGS_E_CAPACITY.  Not
+                        with profile = 1.  Under capture, device blocks come
+                        from those the context cached for the capturing
+                        stream, else are made in relaxed capture mode; the
+                        blocks the captured calls free are kept for later
+                        captures on that stream only (never for eager work)
+                        until the context is destroyed, which must come after
+                        its graphs are destroyed. */
 } msgs_render_opts;
 
 typedef struct {

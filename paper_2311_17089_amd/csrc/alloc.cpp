@@ -5,7 +5,12 @@
 // and the allocation retried).  A freed block records an event on the stream
 // that last used it: the same stream may take it again at once (stream order
 // protects the previous use); another stream takes it only once that event has
-// completed.  Sizes are rounded (powers of two up to 1 MiB, then eighths of the
+// completed.  While a stream is being captured into a graph it takes only its
+// own blocks (an event query would invalidate the capture) and makes a new
+// block in relaxed capture mode when none fits.  A block freed under capture
+// is scratch that the graph's replays write again: it goes back to the cache
+// for later captures on the same stream only, and stays allocated until the
+// context is destroyed (its graphs must be destroyed first).  Sizes are rounded (powers of two up to 1 MiB, then eighths of the
 // next power of two) so that frames of similar size share blocks.  The
 // context's budget counts the rounded bytes of live blocks; that is the figure
 // the server's admission control reads.
@@ -37,6 +42,7 @@ struct DeviceCache::Impl {
     void* p;
     hipStream_t st;
     hipEvent_t ev;
+    bool captured;  // freed while its stream was captured: a graph uses it
   };
   std::mutex mu;
   std::multimap<size_t, Free> free_;
@@ -62,7 +68,7 @@ struct DeviceCache::Impl {
 DeviceCache::DeviceCache() : impl(new Impl()) {}
 
 DeviceCache::~DeviceCache() {
-  release_idle();
+  release_idle(true);
   for (hipEvent_t e : impl->events_) (void)hipEventDestroy(e);
   delete impl;
 }
@@ -72,15 +78,19 @@ size_t DeviceCache::idle_bytes() {
   return impl->cached;
 }
 
-void DeviceCache::release_idle() {
+void DeviceCache::release_idle(bool with_captured) {
   (void)hipDeviceSynchronize();
   std::lock_guard<std::mutex> g(impl->mu);
-  for (auto& kv : impl->free_) {
-    (void)hipFree(kv.second.p);
-    if (kv.second.ev) impl->events_.push_back(kv.second.ev);
+  for (auto it = impl->free_.begin(); it != impl->free_.end();) {
+    if (it->second.captured && !with_captured) {
+      ++it;
+      continue;
+    }
+    (void)hipFree(it->second.p);
+    if (it->second.ev) impl->events_.push_back(it->second.ev);
+    impl->cached -= it->first;
+    it = impl->free_.erase(it);
   }
-  impl->free_.clear();
-  impl->cached = 0;
 }
 
 int DeviceCache::alloc(msgs_context* c, void** out, size_t bytes, hipStream_t st) {
@@ -103,6 +113,10 @@ int DeviceCache::alloc(msgs_context* c, void** out, size_t bytes, hipStream_t st
     auto hi = impl->free_.upper_bound(sz + sz / 2);
     auto pick = impl->free_.end();
     for (auto it = lo; it != hi; ++it) {
+      // a block freed under capture is the scratch of a captured graph, whose
+      // replays write it again: only a later capture on the same stream (whose
+      // replays are ordered with that graph's) may take it
+      if (it->second.captured && !capturing) continue;
       if (it->second.st == st) {
         pick = it;
         break;
@@ -123,14 +137,31 @@ int DeviceCache::alloc(msgs_context* c, void** out, size_t bytes, hipStream_t st
     }
   }
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, sz);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    release_idle();
+  hipError_t e;
+  if (capturing) {
+    // a new block while the stream is captured: hipMalloc is not a stream
+    // operation, so it is made in relaxed capture mode (the block is an
+    // ordinary allocation that the captured work keeps using); no idle-block
+    // release and retry here, since that synchronises the device
+    hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+    (void)hipThreadExchangeStreamCaptureMode(&mode);
+    e = hipMalloc(&p, sz);
+    (void)hipThreadExchangeStreamCaptureMode(&mode);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MSGS_E_NOMEM, std::string("hipMalloc under stream capture: ") +
+                                    hipGetErrorString(e));
+    }
+  } else {
     e = hipMalloc(&p, sz);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      return fail(MSGS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      release_idle(false);
+      e = hipMalloc(&p, sz);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MSGS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+      }
     }
   }
   std::lock_guard<std::mutex> g(impl->mu);
@@ -155,13 +186,14 @@ void DeviceCache::free(msgs_context* c, void* p, hipStream_t st) {
     (void)hipGetLastError();
     cs = hipStreamCaptureStatusNone;
   }
-  hipEvent_t ev = cs == hipStreamCaptureStatusNone ? impl->get_event() : nullptr;
+  const bool captured = cs != hipStreamCaptureStatusNone;
+  hipEvent_t ev = captured ? nullptr : impl->get_event();
   if (ev && hipEventRecord(ev, st) != hipSuccess) {
     (void)hipGetLastError();
     impl->events_.push_back(ev);
     ev = nullptr;
   }
-  impl->free_.insert({sz, Impl::Free{p, st, ev}});
+  impl->free_.insert({sz, Impl::Free{p, st, ev, captured}});
   impl->cached += sz;
 }
 

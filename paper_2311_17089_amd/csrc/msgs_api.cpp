@@ -1,10 +1,10 @@
 // C ABI of libmsgs: contexts, resident scenes, render / backward orchestration
 // and debug getters.  Kernels are in forward.hip, sort.hip and backward.hip.
 //
-// Device memory of frames comes from HIP's stream-ordered allocator
-// (hipMallocAsync / hipFreeAsync on the caller's stream, pool release threshold
-// raised so freed blocks are cached) and is counted against the context's
-// budget, which is what the server's admission control reads.
+// Device memory of frames comes from the context's stream-ordered block cache
+// (alloc.cpp: blocks freed on a stream are reused on it at once and on other
+// streams once their event has completed) and is counted against the
+// context's budget, which is what the server's admission control reads.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -19,7 +19,9 @@ class DeviceCache {
   ~DeviceCache();
   int alloc(msgs_context* c, void** out, size_t bytes, hipStream_t st);
   void free(msgs_context* c, void* p, hipStream_t st);
-  void release_idle();
+  // frees the idle blocks; those freed under stream capture (scratch of a
+  // captured graph) only with with_captured, when no graph can replay again
+  void release_idle(bool with_captured);
   size_t idle_bytes();
 
  private:

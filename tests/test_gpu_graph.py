@@ -225,3 +225,57 @@ def test_frames_captured_on_several_streams():
     for fr in frames:
         fr.release()
     dsc.close()
+
+
+def test_capture_with_a_cold_block_cache_and_eager_work_between_replays():
+    """A frame captured with nothing cached for its stream (new blocks are
+    made during the capture), replayed with eager renders and backward passes
+    of another view on the same stream in between: replays and eager results
+    must both match their references, and the eager frame kept across a replay
+    must still give its own gradients (scratch freed inside the capture is not
+    handed to eager work)."""
+    _say("  capture with a cold block cache, eager work between replays")
+    ctx = M.Context(0)
+    dsc = _scene(ctx)
+    (cam0, d0), (cam1, d1) = _views()[:2]
+    dl0 = torch.randn((240 // d0, 320 // d0, 3), generator=torch.Generator().manual_seed(41)).cuda()
+    dl1 = torch.randn((240 // d1, 320 // d1, 3), generator=torch.Generator().manual_seed(42)).cuda()
+    ref = []
+    for cam, d, dl in ((cam0, d0, dl0), (cam1, d1, dl1)):
+        img, fr = M.render(ctx, dsc, cam, downscale=d, keep_frame=True)
+        cap = int(fr.stats()["n_instances"] * 1.25) + 64
+        g = M.render_backward(ctx, fr, dl)
+        torch.cuda.synchronize()
+        ref.append((cap, img.cpu().numpy(), {k: v.cpu().numpy() for k, v in g.items()}))
+        fr.release()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    out0 = torch.empty((240 // d0, 320 // d0, 3), device="cuda")
+    g0 = {k: torch.empty_like(dsc.t[k]) for k in NAMES}
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        _, f0 = M.render(ctx, dsc, cam0, downscale=d0, keep_frame=True, capacity=ref[0][0],
+                         out=out0, stream=s)
+        M.render_backward(ctx, f0, dl0, stream=s, grads=g0)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        with torch.cuda.stream(s):
+            out0.fill_(-1.0)
+            # an eager frame of the other view on the capture stream, kept
+            # across the replay
+            img1, f1 = M.render(ctx, dsc, cam1, downscale=d1, keep_frame=True, stream=s,
+                                capacity=ref[1][0])
+            graph.replay()
+            g1 = M.render_backward(ctx, f1, dl1, stream=s)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out0.cpu().numpy(), ref[0][1])
+        np.testing.assert_array_equal(img1.cpu().numpy(), ref[1][1])
+        for k in NAMES:
+            np.testing.assert_array_equal(g0[k].cpu().numpy(), ref[0][2][k])
+            np.testing.assert_array_equal(g1[k].cpu().numpy(), ref[1][2][k])
+        f1.release()
+    _say("  2 replays and the eager frames between them match their references")
+    del graph
+    torch.cuda.synchronize()
+    f0.release()
+    dsc.close()
