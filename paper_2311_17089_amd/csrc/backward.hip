@@ -34,6 +34,7 @@ namespace msgs {
 constexpr int kNP = 9;          // partials per instance
 constexpr int kBB = 128;        // instances per LDS batch of the replay
 constexpr uint32_t kSmallSeg = 64;
+constexpr int kSegRound = 8;    // written partials loaded together per round
 
 // Sum of v over the 64 lanes of the wave, valid in lane 63 (DPP row sums,
 // then row broadcasts 15 and 31).
@@ -291,15 +292,6 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
   }
 }
 
-// s += the nine partials of one slot (three float3, 36 bytes)
-__device__ __forceinline__ void acc9(float* s, const float* partial, int64_t slot) {
-  const float3* P = (const float3*)(partial + slot * kNP);
-  const float3 a = P[0], b = P[1], c = P[2];
-  s[0] += a.x; s[1] += a.y; s[2] += a.z;
-  s[3] += b.x; s[4] += b.y; s[5] += b.z;
-  s[6] += c.x; s[7] += c.y; s[8] += c.z;
-}
-
 __device__ __forceinline__ void store3(float* gsum, int64_t k, const float* s) {
   float4* G = (float4*)gsum + k * 3;
   G[0] = make_float4(s[0], s[1], s[2], s[3]);
@@ -335,13 +327,13 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
     const uint32_t lo = e0 > w0 ? e0 - w0 : 0u;
     const uint32_t hi = e1 - w0 >= 32u ? 32u : e1 - w0;
     bits &= (hi == 32u ? ~0u : ((1u << hi) - 1u)) & (~0u << lo);
-    // up to four written slots per round: their loads are all issued before
-    // the first sum needs one, and the sums still run in slot order
+    // up to kSegRound written slots per round: their loads are all issued
+    // before the first sum needs one, and the sums still run in slot order
     while (bits) {
-      uint32_t e[4];
+      uint32_t e[kSegRound];
       int m = 0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kSegRound; ++u) {
         e[u] = w0;
         if (bits) {
           e[u] = w0 + (uint32_t)__ffs(bits) - 1u;
@@ -349,9 +341,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
           m = u + 1;
         }
       }
-      float3 P[4][3];
+      float3 P[kSegRound][3];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kSegRound; ++u) {
         if (u < m) {
           const float3* p = (const float3*)(partial + (int64_t)e[u] * kNP);
           P[u][0] = p[0];
@@ -360,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kSegRound; ++u) {
         if (u < m) {
           s[0] += P[u][0].x; s[1] += P[u][0].y; s[2] += P[u][0].z;
           s[3] += P[u][1].x; s[4] += P[u][1].y; s[5] += P[u][1].z;
@@ -387,9 +379,33 @@ __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
     float s[kNP];
 #pragma unroll
     for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
-    for (uint32_t t = threadIdx.x; t < c; t += kBlock) {
-      const uint32_t e = e0 + t;
-      if ((wmask[e >> 5] >> (e & 31u)) & 1u) acc9(s, partial, (int64_t)e);
+    // four strided slots per thread and round, their loads issued together
+    for (uint32_t t0 = threadIdx.x; t0 < c; t0 += 4 * kBlock) {
+      bool w[4];
+      float3 P[4][3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t t = t0 + (uint32_t)u * kBlock;
+        const uint32_t e = e0 + t;
+        w[u] = t < c && ((wmask[e >> 5] >> (e & 31u)) & 1u);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (w[u]) {
+          const float3* p = (const float3*)(partial + (int64_t)(e0 + t0 + (uint32_t)u * kBlock) * kNP);
+          P[u][0] = p[0];
+          P[u][1] = p[1];
+          P[u][2] = p[2];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (w[u]) {
+          s[0] += P[u][0].x; s[1] += P[u][0].y; s[2] += P[u][0].z;
+          s[3] += P[u][1].x; s[4] += P[u][1].y; s[5] += P[u][1].z;
+          s[6] += P[u][2].x; s[7] += P[u][2].y; s[8] += P[u][2].z;
+        }
+      }
     }
 #pragma unroll
     for (int q = 0; q < kNP; ++q) {
