@@ -35,9 +35,12 @@ sys.path.insert(0, ROOT)
 DOWNSCALES = (1, 4, 16, 64)
 W_FULL, H_FULL, FOCAL = 1600, 1064, 1875.0
 HBM_PEAK_GBS = 8000.0
-# fp32 vector rate without packed math: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
-# x 2 flops per fma (the library is compiled with packed fp32 disabled).
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# fp32 vector peak: 256 CUs x 4 SIMD x 32 fp32 lanes per cycle x 2.4 GHz x 2
+# flops per fma = 157.3 TFLOP/s.  The library is compiled with packed fp32
+# disabled, but a wave64 fp32 fma still issues every ~2 cycles on gfx950 (a
+# probe of eight independent fma chains per thread measured 2.45 cycles), so
+# the unpacked rate is this same peak.
+ALU_PEAK_TFLOPS = 256 * 4 * 32 * 2.4e9 * 2 / 1e12
 # algorithmic fp32 flops of the compositing loop (fma = 2): every evaluated
 # (pixel, instance) pair costs the offset and quadratic form (11); every
 # accumulated contribution adds exp (19), alpha, transmittance and colour (10).
