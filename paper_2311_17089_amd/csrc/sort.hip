@@ -26,6 +26,18 @@ namespace msgs {
 
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+
+// Digits of pass p of npass = ceil((end - begin) / 8) passes over key bits
+// [begin, end): the bits are split as evenly as the pass count allows (13
+// bits as 7 + 6, not 8 + 5), so that every pass scatters into as few buckets
+// as possible and the runs it writes per bucket are as long as possible.
+__host__ __device__ inline void pass_digits(int begin, int end, int p, int& shift, int& nbits) {
+  const int total = end - begin;
+  const int npass = (total + kRadixBits - 1) / kRadixBits;
+  const int base = total / npass, extra = total % npass;
+  shift = begin + p * base + (p < extra ? p : extra);
+  nbits = base + (p < extra ? 1 : 0);
+}
 constexpr unsigned long long kFlagA = 1ull << 62;
 constexpr unsigned long long kFlagP = 2ull << 62;
 constexpr unsigned long long kValMask = (1ull << 62) - 1;
@@ -210,8 +222,8 @@ __global__ __launch_bounds__(kBlock) void k_os_hist(const uint32_t* keys, const 
     for (int u = 0; u < kHistUnroll; ++u) {
       if (b + u * kBlock + threadIdx.x < i1) {
         for (int p = 0; p < npass; ++p) {
-          const int sh = begin_bit + p * kRadixBits;
-          const int nb = min(kRadixBits, end_bit - sh);
+          int sh, nb;
+          pass_digits(begin_bit, end_bit, p, sh, nb);
           atomicAdd(&h[p][wave][(kk[u] >> sh) & ((1u << nb) - 1u)], 1u);
         }
       }
@@ -506,8 +518,8 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
     uint32_t* counts = rowtot + kRadix;
     uint32_t* starts = counts + kRadix * nblk;
     for (int p = 0; p < npass; ++p) {
-      const int b = begin_bit + p * kRadixBits;
-      const int nbits = std::min(kRadixBits, end_bit - b);
+      int b, nbits;
+      pass_digits(begin_bit, end_bit, p, b, nbits);
       if (items == 16)
         hipLaunchKernelGGL(k_rs_count<16>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, d_n,
                            nmax, b, nbits, counts, nblk);
@@ -537,8 +549,8 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
   hipLaunchKernelGGL(k_os_hist, dim3(hgrid), dim3(kBlock), 0, st, keys, d_n, nmax, begin_bit,
                      end_bit, ghist);
   for (int p = 0; p < npass; ++p) {
-    const int b = begin_bit + p * kRadixBits;
-    const int nbits = std::min(kRadixBits, end_bit - b);
+    int b, nbits;
+    pass_digits(begin_bit, end_bit, p, b, nbits);
     if (items == 16)
       hipLaunchKernelGGL((k_os_pass<16, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                          vin, kout, vout, d_n, nmax, b, nbits, ghist + p * kRadix,
