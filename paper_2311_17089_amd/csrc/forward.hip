@@ -248,14 +248,30 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* p, int64_t n, uin
 }
 
 // The instances of the list: *d_n when given (at most nmax), else nmax.
+// Four consecutive keys per thread, with the key before and the key after
+// them, so that every key is read about once.
+constexpr int kRangeItems = 4;
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* tkeys, const uint32_t* d_n,
                                                    uint32_t nmax, uint2* ranges) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   const uint32_t ninst = d_n ? min(*d_n, nmax) : nmax;
-  if (i >= ninst) return;
-  const uint32_t t = tkeys[i];
-  if (i == 0 || tkeys[i - 1] != t) ranges[t].x = i;
-  if (i == ninst - 1 || tkeys[i + 1] != t) ranges[t].y = i + 1;
+  const uint64_t i0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * kRangeItems;
+  if (i0 >= ninst) return;
+  const uint32_t b = (uint32_t)i0;
+  uint32_t k[kRangeItems + 2];  // k[0] = key b - 1, k[1 + j] = key b + j, then key b + 4
+#pragma unroll
+  for (int j = 0; j < kRangeItems + 2; ++j) {
+    const int64_t i = (int64_t)b - 1 + j;
+    k[j] = (i >= 0 && i < (int64_t)ninst) ? tkeys[i] : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int j = 0; j < kRangeItems; ++j) {
+    const uint32_t i = b + (uint32_t)j;
+    if (i < ninst) {
+      const uint32_t t = k[1 + j];
+      if (i == 0 || k[j] != t) ranges[t].x = i;
+      if (i == ninst - 1 || k[2 + j] != t) ranges[t].y = i + 1;
+    }
+  }
 }
 
 // Tile for a workgroup: workgroups are dispatched round-robin over the 8 XCDs,
@@ -533,8 +549,8 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
 void launch_ranges(const uint32_t* tkeys, const uint32_t* d_n, uint32_t nmax, uint2* ranges,
                    hipStream_t st) {
   if (nmax == 0) return;
-  hipLaunchKernelGGL(k_ranges, dim3(grid_for(nmax)), dim3(kBlock), 0, st, tkeys, d_n, nmax,
-                     ranges);
+  hipLaunchKernelGGL(k_ranges, dim3(grid_for(((int64_t)nmax + kRangeItems - 1) / kRangeItems)),
+                     dim3(kBlock), 0, st, tkeys, d_n, nmax, ranges);
 }
 
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
