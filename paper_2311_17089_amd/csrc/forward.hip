@@ -198,7 +198,11 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* order, const ui
                                                  const uint32_t* d_nvis, const uint32_t* count,
                                                  const uint2* rect, int Tx, uint32_t* tkeys,
                                                  uint32_t* tvals, uint32_t* emit_base,
-                                                 uint32_t cap) {
+                                                 uint32_t cap, unsigned long long* ctr_fit) {
+  // fixed capacity: the instances that fit, ctr[7] = min(ctr[3], cap), for
+  // the sort and the ranges that follow
+  if (ctr_fit && blockIdx.x == 0 && threadIdx.x == 0)
+    ctr_fit[7] = ctr_fit[3] < (unsigned long long)cap ? ctr_fit[3] : (unsigned long long)cap;
   __shared__ uint32_t sb[kBlock / 64][64], sk[kBlock / 64][64];
   __shared__ uint2 sr[kBlock / 64][64];
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -447,32 +451,6 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
   if (lane == 0 && e64) atomicAdd(sl + 3, e64);
 }
 
-// Totals of the counter slots: ctr[0] selected, ctr[1] blends, ctr[4] visits,
-// ctr[5] evaluations, ctr[6] prefiltered (fixed summation order).
-__global__ __launch_bounds__(kCtrSlots) void k_sum_slots(const unsigned long long* slots,
-                                                         unsigned long long* ctr) {
-  __shared__ unsigned long long part[5][kCtrSlots / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    unsigned long long x = slots[threadIdx.x * kSlotW + q];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) part[q][wave] = x;
-  }
-  __syncthreads();
-  if (threadIdx.x < 5) {
-    unsigned long long t = 0;
-    for (int w = 0; w < kCtrSlots / 64; ++w) t += part[threadIdx.x][w];
-    const int dst[5] = {0, 1, 4, 5, 6};
-    ctr[dst[threadIdx.x]] = t;
-  }
-}
-
-void launch_sum_slots(const unsigned long long* slots, unsigned long long* ctr, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(kCtrSlots), 0, st, slots, ctr);
-}
-
 __global__ __launch_bounds__(kBlock) void k_debug_exp(const float* x, float* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) y[i] = exp_c(x[i]);
@@ -508,19 +486,11 @@ void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
 
 void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_nvis,
                  int64_t nmax, const uint32_t* count, const uint2* rect, int Tx, uint32_t* tkeys,
-                 uint32_t* tvals, uint32_t* emit_base, uint32_t cap, hipStream_t st) {
+                 uint32_t* tvals, uint32_t* emit_base, uint32_t cap, unsigned long long* ctr_fit,
+                 hipStream_t st) {
   if (nmax == 0) return;
   hipLaunchKernelGGL(k_emit, dim3(grid_for(nmax)), dim3(kBlock), 0, st, order, off, d_nvis, count,
-                     rect, Tx, tkeys, tvals, emit_base, cap);
-}
-
-// Instances that fit: ctr[7] = min(ctr[3], cap) (fixed-capacity renders).
-__global__ void k_cap_clamp(unsigned long long* ctr, unsigned long long cap) {
-  if (threadIdx.x == 0) ctr[7] = ctr[3] < cap ? ctr[3] : cap;
-}
-
-void launch_cap_clamp(unsigned long long* ctr, unsigned long long cap, hipStream_t st) {
-  hipLaunchKernelGGL(k_cap_clamp, dim3(1), dim3(64), 0, st, ctr, cap);
+                     rect, Tx, tkeys, tvals, emit_base, cap, ctr_fit);
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero(ZeroList z, int64_t total) {

@@ -217,7 +217,7 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   // instances that fit); emission, sort and ranges never pass the capacity
   const uint32_t* d_inst = f->capacity ? (const uint32_t*)&f->ctr[7] : nullptr;
   launch_emit(f->order, f->off_d, d_nvis, n, f->count, f->rect, v.Tx, k0, v0, f->emit_base,
-              f->capacity ? (uint32_t)I : 0xFFFFFFFFu, st);
+              f->capacity ? (uint32_t)I : 0xFFFFFFFFu, f->capacity ? f->ctr : nullptr, st);
   mark(f, 5);
   radix_sort_pairs(k0, v0, k1, v1, d_inst, I, 0, bits, stmp, st, true);
   mark(f, 6);
@@ -228,7 +228,6 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
                f->ctr + 8, st);
   mark(f, 8);
-  launch_sum_slots(f->ctr + 8, f->ctr, st);
   f->ctx->cache.free(f->ctx, tmp.base, st);
   f->ctx->cache.free(f->ctx, f->tmp_block, st);
   f->tmp_block = nullptr;
@@ -530,7 +529,6 @@ int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
     // no host synchronisation: tile lists sized by the capacity
     f->n_vis = f->n;
     f->n_inst = f->capacity;
-    launch_cap_clamp(f->ctr, (unsigned long long)f->capacity, f->st);
   } else if (rc == MSGS_OK) {
     unsigned long long* hp = pinned_slot();
     if (!hp) {
@@ -724,9 +722,16 @@ int msgs_frame_stats(const msgs_frame* f, msgs_stats* out) {
   if (!f || !out) return fail(MSGS_E_INVALID, "null argument");
   int rc = frame_sync(f);
   if (rc != MSGS_OK) return rc;
-  unsigned long long h[7];
-  hipError_t e = hipMemcpy(h, f->ctr, sizeof h, hipMemcpyDeviceToHost);
+  // the totals, then the per-slot counters of the projection and blending
+  // kernels (selected, blends, visits, evaluations, prefiltered), summed here
+  std::vector<unsigned long long> c(8 + (size_t)kSlotW * kCtrSlots);
+  hipError_t e = hipMemcpy(c.data(), f->ctr, c.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(e, "stats readback");
+  unsigned long long h[7] = {0, 0, c[2], c[3], 0, 0, 0};
+  const int dst[5] = {0, 1, 4, 5, 6};
+  for (int sl = 0; sl < kCtrSlots; ++sl)
+    for (int q = 0; q < 5; ++q) h[dst[q]] += c[8 + (size_t)sl * kSlotW + q];
   for (int i = 0; i < 12; ++i) out->stage_us[i] = 0.0f;
   if (f->profile) {
     auto span = [&](int a, int b) {

@@ -15,10 +15,11 @@ void launch_project(const SceneView& s, const ViewParams& v, uint8_t* sel, uint3
                     unsigned long long* slots, hipStream_t st);
 void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
                     const uint32_t* blk_off, uint32_t* keys, uint32_t* vals, hipStream_t st);
+// ctr_fit (fixed-capacity renders, else null): ctr_fit[7] = min(ctr_fit[3], cap)
 void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_nvis,
                  int64_t nmax, const uint32_t* count, const uint2* rect, int Tx, uint32_t* tkeys,
-                 uint32_t* tvals, uint32_t* emit_base, uint32_t cap, hipStream_t st);
-void launch_cap_clamp(unsigned long long* ctr, unsigned long long cap, hipStream_t st);
+                 uint32_t* tvals, uint32_t* emit_base, uint32_t cap, unsigned long long* ctr_fit,
+                 hipStream_t st);
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 // Up to kZeroSegs device regions cleared by one launch (the counters, status
 // words and flags that a render or a backward pass needs zeroed up front).
@@ -41,7 +42,6 @@ void launch_ranges(const uint32_t* tkeys, const uint32_t* d_n, uint32_t nmax, ui
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
                   unsigned long long* slots, hipStream_t st);
-void launch_sum_slots(const unsigned long long* slots, unsigned long long* ctr, hipStream_t st);
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st);
 void launch_debug_log(const float* x, float* y, int64_t n, hipStream_t st);
 
