@@ -161,6 +161,7 @@ int render_phase1(msgs_frame* f) {
   // counters and every status word of the phase, cleared by one launch
   ZeroList z;
   z.add(f->ctr, 2 * (8 + kSlotW * kCtrSlots));
+  z.add(f->ranges, (int64_t)ntile * 2);  // tiles with no instance keep (0, 0)
   z.add(f->scan_tmp, scan_zero_words(nb));
   z.add(f->scan_tmp2, scan_zero_words(n));
   z.add(f->sort_tmp, radix_zero_words(n, radix_passes(0, 32)));
@@ -208,8 +209,8 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   uint32_t* k1 = even ? kb : ka;
   uint32_t* v1 = even ? vb : va;
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
+  // the status words of a look-back tile sort (none for reduce-then-scan)
   ZeroList z;
-  z.add(f->ranges, (int64_t)ntile * 2);
   z.add(stmp, radix_zero_words(I, radix_passes(0, bits)));
   launch_zero(z, st);
   mark(f, 4);
