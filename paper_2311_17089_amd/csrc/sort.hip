@@ -41,8 +41,8 @@ __host__ __device__ inline void pass_digits(int begin, int end, int p, int& shif
 constexpr unsigned long long kFlagA = 1ull << 62;
 constexpr unsigned long long kFlagP = 2ull << 62;
 constexpr unsigned long long kValMask = (1ull << 62) - 1;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems;  // 4096
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;  // 2048: more workgroups share the gathers
 
 __device__ __forceinline__ unsigned long long ld_status(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
