@@ -475,7 +475,7 @@ void scan_excl_u32(const uint32_t* in, const uint32_t* gather, uint32_t* out, co
 }
 
 // Tiles from which a sort pass switches to reduce-then-scan.
-constexpr int64_t kRtsMinTiles = 64;
+constexpr int64_t kRtsMinTiles = 512;
 
 // Layout of the temporary block.  Onesweep: [global histograms][status words
 // of every pass][tickets], all zeroed.  Reduce-then-scan: [digit totals][digit

@@ -2,8 +2,8 @@
 MI355X), through msgs_debug_sort_pairs, against numpy's stable argsort of the
 masked key bits.  Bit-exact: keys and values both.
 
-Sizes cover the single-pass look-back path (fewer than 64 tiles), the
-reduce-then-scan path (64 tiles and more, with 2048- and 4096-key tiles),
+Sizes cover the single-pass look-back path (fewer than 512 tiles), the
+reduce-then-scan path (512 tiles and more, with 2048- and 4096-key tiles),
 tile boundaries, ragged tails, heavy key duplication (stability), partial bit
 ranges, and a device-side count smaller than the arrays.
 """
@@ -41,8 +41,8 @@ def _ref(keys, begin, end, n):
     (2048, 0, 13, 64),
     (2049, 0, 32, 1000),
     (4097, 8, 24, 0),
-    (131_071, 0, 32, 0),                # 64 tiles of 2048: reduce-then-scan
-    ((1 << 20) - 1, 0, 32, 0),
+    (131_071, 0, 32, 0),                # 64 tiles of 2048: look-back
+    ((1 << 20) - 1, 0, 32, 0),          # 512 tiles of 2048: reduce-then-scan
     (3_000_001, 0, 13, 6700),           # tile-key shape, many duplicates
     (5_000_003, 0, 32, 0),              # 4096-key tiles
     (5_000_003, 3, 17, 300),
