@@ -142,11 +142,9 @@ int render_phase1(msgs_frame* f) {
   keep.add(&f->off_d, n * 4);
   Carve tmp;
   tmp.add(&f->blk_vis, nb * 4);
-  tmp.add(&f->blk_off, nb * 4);
   tmp.add(&f->dkeys[0], n * 4);
   tmp.add(&f->dkeys[1], n * 4);
   tmp.add(&f->dvals_alt, n * 4);
-  tmp.add(&f->scan_tmp, scan_tmp_bytes(nb));
   tmp.add(&f->scan_tmp2, scan_tmp_bytes(n));
   tmp.add(&f->sort_tmp, radix_tmp_bytes(n, radix_passes(0, 32)));
   int rc = keep.alloc(f->ctx, st);
@@ -162,15 +160,13 @@ int render_phase1(msgs_frame* f) {
   ZeroList z;
   z.add(f->ctr, 2 * (8 + kSlotW * kCtrSlots));
   z.add(f->ranges, (int64_t)ntile * 2);  // tiles with no instance keep (0, 0)
-  z.add(f->scan_tmp, scan_zero_words(nb));
   z.add(f->scan_tmp2, scan_zero_words(n));
   z.add(f->sort_tmp, radix_zero_words(n, radix_passes(0, 32)));
   launch_zero(z, st);
   mark(f, 0);
   launch_project(f->scene->view, v, f->sel, f->count, f->depthkey, f->rec, f->rect, f->blk_vis,
                  f->ctr + 8, st);
-  scan_excl_u32(f->blk_vis, nullptr, f->blk_off, nullptr, nb, &f->ctr[2], f->scan_tmp, st, true);
-  launch_compact(f->count, f->depthkey, n, f->blk_off, f->dkeys[0], dv0, st);
+  launch_compact(f->count, f->depthkey, n, f->blk_vis, f->dkeys[0], dv0, &f->ctr[2], st);
   mark(f, 1);
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
   radix_sort_pairs(f->dkeys[0], vin, f->dkeys[1], valt, d_nvis, n, 0, 32, f->sort_tmp, st, true);
@@ -232,9 +228,9 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   f->ctx->cache.free(f->ctx, tmp.base, st);
   f->ctx->cache.free(f->ctx, f->tmp_block, st);
   f->tmp_block = nullptr;
-  f->blk_vis = f->blk_off = f->dvals_alt = nullptr;
+  f->blk_vis = f->dvals_alt = nullptr;
   f->dkeys[0] = f->dkeys[1] = nullptr;
-  f->scan_tmp = f->scan_tmp2 = f->sort_tmp = nullptr;
+  f->scan_tmp2 = f->sort_tmp = nullptr;
   return MSGS_OK;
 }
 

@@ -92,10 +92,8 @@ struct msgs_frame {
   // temporaries of the render (one block, released after blending)
   void* tmp_block = nullptr;
   uint32_t* blk_vis = nullptr;
-  uint32_t* blk_off = nullptr;
   uint32_t* dkeys[2] = {nullptr, nullptr};
   uint32_t* dvals_alt = nullptr;
-  void* scan_tmp = nullptr;
   void* scan_tmp2 = nullptr;
   void* sort_tmp = nullptr;
 };
