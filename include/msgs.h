@@ -211,7 +211,13 @@ int msgs_render(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
  *   dL_drgb  device [H_d][W_d][3] fp32
  *   out      device gradient planes (see msgs_grads)
  * The scene's parameters must not have changed since the render.  The per-tile
- * partial sums are reduced per Gaussian without atomics (deterministic). */
+ * partial sums are reduced per Gaussian without atomics (deterministic).
+ * Stream order: `stream` may differ from the stream the frame was rendered on;
+ * the backward then waits for the render's work on the frame's stream, and
+ * the frame's stream waits for the backward, so msgs_frame_release may be
+ * called right after this call returns (the frame's buffers go back to the
+ * context only once the backward has read them).  dL_drgb and the gradient
+ * planes are ordered by `stream` alone. */
 int msgs_render_backward(msgs_context* ctx, const msgs_frame* frame, const float* dL_drgb,
                          const msgs_grads* out, void* stream);
 
@@ -228,7 +234,8 @@ int msgs_render_backward(msgs_context* ctx, const msgs_frame* frame, const float
  *   dL_drgb  host array of nviews device pointers, [H_d][W_d][3] fp32 each
  *   nviews   >= 1 (else MSGS_E_INVALID)
  * Temporary device memory: 48 bytes per Gaussian per view, 4 per Gaussian,
- * and 36 bytes plus one bit per tile instance of the largest frame. */
+ * and 36 bytes plus one bit per tile instance of the largest frame.  Stream
+ * order as for msgs_render_backward, for every frame. */
 int msgs_render_backward_views(msgs_context* ctx, const msgs_frame* const* frames,
                                const float* const* dL_drgb, int nviews, const msgs_grads* out,
                                void* stream);
@@ -329,7 +336,7 @@ int msgs_debug_exp(const float* x, float* y, int64_t n, void* stream);
 int msgs_debug_log(const float* x, float* y, int64_t n, void* stream);
 /* The library's stable LSD radix sort of (u32 key, u32 value) pairs by key
  * bits [begin_bit, end_bit), in place on device arrays of nmax entries.  Sorts
- * the first *d_n entries when d_n (device u32, at most nmax) is non-null, else
+ * the first min(*d_n, nmax) entries when d_n (device u32) is non-null, else
  * all nmax; entries past the count are left unspecified.  The sort that orders
  * Gaussians by depth and tile instances by tile (Sec. 3.1); for verification.
  * Temporary memory comes from the context.  Synchronises `stream`. */

@@ -71,6 +71,8 @@ def lib():
         L.or_trace.argtypes = [P, P, P, C.c_int64, P, C.c_int64, P, P, P, C.c_int]
         L.or_trace.restype = C.c_int64
         L.or_update_range.argtypes = [P, P, P, P, P, C.c_int]
+        L.or_clamp_tile.argtypes = [C.c_float, C.c_int]
+        L.or_clamp_tile.restype = C.c_int
         _lib = L
     return _lib
 
@@ -181,10 +183,19 @@ def keys(scene, cam, downscale=1, selective=True, lowpass=0.3, near=0.2, nthread
     return k[:tot], v[:tot]
 
 
+def clamp_tile(v: float, T: int) -> int:
+    """The rectangle rule's float-to-tile conversion: clamp to [-1, T] with
+    fmin/fmax semantics (a NaN operand yields the bound), then truncate.
+    Pinned by hand cases in test_oracle_pipeline."""
+    return int(lib().or_clamp_tile(float(v), int(T)))
+
+
 def tile_ranges(keys_sorted: np.ndarray, n_tiles: int) -> np.ndarray:
     """[n_tiles][2] half-open ranges of each tile in the sorted key list; (0, 0)
     for empty tiles.  Plain definition: the first and one-past-last position of
-    each tile id."""
+    each tile id (Sec. 3.1: each tile reads its own stretch of the list sorted
+    by tile and depth).  Pinned by hand-worked lists (empty, one tile, gaps,
+    the last tile) and by a position-by-position scan in test_oracle_pipeline."""
     r = np.zeros((n_tiles, 2), np.uint32)
     if keys_sorted.size == 0:
         return r

@@ -202,6 +202,15 @@ struct Cam {
 
 bool make_cam(const or_camera* c, const or_opts* o, Cam* k) {
   if (o->downscale < 1) return false;
+  // a camera with a non-finite entry is rejected: with a NaN centre every skip
+  // test of the compositing is false, so nothing bounds the drawn pixels
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(c->R[i])) return false;
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(c->t[i])) return false;
+  if (!std::isfinite(c->fx) || !std::isfinite(c->fy) || !std::isfinite(c->cx) ||
+      !std::isfinite(c->cy))
+    return false;
   std::memcpy(k->R, c->R, sizeof k->R);
   std::memcpy(k->t, c->t, sizeof k->t);
   float d = (float)o->downscale;
@@ -446,6 +455,10 @@ void set_threads(int nthreads) {
 extern "C" {
 
 int or_version(void) { return 1; }
+
+// The tile-index conversion of the rectangle rule: clamp to [-1, T] with
+// fmin/fmax semantics (a NaN operand yields the bound), then truncate.
+int or_clamp_tile(float v, int T) { return (int)clampf_to(v, -1.0f, (float)T); }
 
 int or_max_threads(void) {
 #ifdef _OPENMP

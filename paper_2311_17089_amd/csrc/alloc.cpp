@@ -201,13 +201,24 @@ void DeviceCache::free(msgs_context* c, void* p, hipStream_t st) {
 size_t Carve::add(void** slot, size_t bytes) {
   const size_t off = total;
   total += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
-  parts.push_back({slot, off});
+  if (nparts < kMaxParts)
+    parts[nparts++] = {slot, off};
+  else
+    overflow = true;
   return off;
+}
+
+int Carve::place(void* b) {
+  if (overflow) return fail(MSGS_E_INVALID, "internal: buffer layout has too many parts");
+  base = b;
+  for (int i = 0; i < nparts; ++i) *parts[i].first = (char*)base + parts[i].second;
+  return MSGS_OK;
 }
 
 thread_local AdmitWaiter* t_waiter = nullptr;
 
 int Carve::alloc(msgs_context* c, hipStream_t st) {
+  if (overflow) return fail(MSGS_E_INVALID, "internal: buffer layout has too many parts");
   for (;;) {
     int rc = c->cache.alloc(c, &base, total, st);
     if (rc == MSGS_OK) break;
@@ -216,7 +227,7 @@ int Carve::alloc(msgs_context* c, hipStream_t st) {
     if (w == MemWait::kAbort) return kRequeue;
     if (w == MemWait::kFail) return rc;
   }
-  for (auto& p : parts) *p.first = (char*)base + p.second;
+  for (int i = 0; i < nparts; ++i) *parts[i].first = (char*)base + parts[i].second;
   return MSGS_OK;
 }
 

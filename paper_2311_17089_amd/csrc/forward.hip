@@ -170,11 +170,15 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, u
 
 // Order-preserving compaction of the drawable Gaussians (tile count > 0).
 // blk_vis[b] is the drawable count of block b of the projection (the same 256
-// Gaussians as block b here); each block sums the counts of the blocks before
-// it itself (a few KB, read from L2), so no separate scan runs, and the last
-// block writes the total to *total.
+// Gaussians as block b here).  Up to kCompactInKernelBlocks blocks, each block
+// sums the counts of the blocks before it itself (at most 16 KB, read from L2),
+// so no separate scan runs, and the last block writes the total to *total.
+// Above that the block sums grow with the square of the block count, so the
+// caller scans blk_vis first (blk_pre = its exclusive prefix, the scan writes
+// the total) and each block reads its own start.
 __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* count, const uint32_t* depthkey,
                                                     int64_t n, const uint32_t* blk_vis,
+                                                    const uint32_t* blk_pre,
                                                     uint32_t* keys_out, uint32_t* vals_out,
                                                     unsigned long long* total) {
   __shared__ uint32_t wsum[kBlock / 64];
@@ -186,15 +190,20 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* count, const
   const uint32_t wrank = (uint32_t)__popcll(m & __lanemask_lt());
   if (lane == 0) wsum[wave] = (uint32_t)__popcll(m);
   uint32_t pre = 0;
-  for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kBlock) pre += blk_vis[i];
+  if (!blk_pre)
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kBlock) pre += blk_vis[i];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) pre += (uint32_t)__shfl_xor((int)pre, o, 64);
   if (lane == 0) wpre[wave] = pre;
   __syncthreads();
   uint32_t base = 0;
+  if (blk_pre) {
+    base = blk_pre[blockIdx.x];
+  } else {
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) base += wpre[w];
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    for (int w = 0; w < kBlock / 64; ++w) base += wpre[w];
+  }
+  if (!blk_pre && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
     uint32_t own = 0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) own += wsum[w];
@@ -498,11 +507,14 @@ void launch_project(const SceneView& s, const ViewParams& v, uint8_t* sel, uint3
 }
 
 void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
-                    const uint32_t* blk_vis, uint32_t* keys, uint32_t* vals,
-                    unsigned long long* total, hipStream_t st) {
+                    const uint32_t* blk_vis, uint32_t* blk_pre, void* scan_tmp, uint32_t* keys,
+                    uint32_t* vals, unsigned long long* total, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_compact, dim3(grid_for(n)), dim3(kBlock), 0, st, count, depthkey, n,
-                     blk_vis, keys, vals, total);
+  const int64_t nb = grid_for(n);
+  const bool scanned = nb > kCompactInKernelBlocks;
+  if (scanned) scan_excl_u32(blk_vis, nullptr, blk_pre, nullptr, nb, total, scan_tmp, st, true);
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)nb), dim3(kBlock), 0, st, count, depthkey, n,
+                     blk_vis, scanned ? blk_pre : nullptr, keys, vals, total);
 }
 
 void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_nvis,

@@ -58,8 +58,16 @@ int make_view(const msgs_camera* cam, const msgs_render_opts* o, int n_levels, V
   if (cam->width <= 0 || cam->height <= 0) return fail(MSGS_E_INVALID, "empty camera");
   const int W = cam->width / o->downscale, H = cam->height / o->downscale;
   if (W <= 0 || H <= 0) return fail(MSGS_E_INVALID, "downscaled frame is empty");
-  if (!(o->lowpass >= 0.0f) || !(o->near_z > 0.0f))
-    return fail(MSGS_E_INVALID, "lowpass must be >= 0 and near_z > 0");
+  if (!(o->lowpass >= 0.0f) || !(o->near_z > 0.0f) || !std::isfinite(o->lowpass) ||
+      !std::isfinite(o->near_z))
+    return fail(MSGS_E_INVALID, "lowpass must be finite and >= 0, near_z finite and > 0");
+  // a non-finite camera would make the projected centre NaN, for which no
+  // skip test of the compositing holds and no tile rectangle is defined
+  bool finite = std::isfinite(cam->fx) && std::isfinite(cam->fy) && std::isfinite(cam->cx) &&
+                std::isfinite(cam->cy);
+  for (int i = 0; i < 9; ++i) finite = finite && std::isfinite(cam->R[i]);
+  for (int i = 0; i < 3; ++i) finite = finite && std::isfinite(cam->t[i]);
+  if (!finite) return fail(MSGS_E_INVALID, "camera entries must be finite");
   std::memcpy(v->R, cam->R, sizeof v->R);
   std::memcpy(v->t, cam->t, sizeof v->t);
   const float d = (float)o->downscale;
@@ -100,6 +108,28 @@ void frame_free_all(msgs_frame* f) {
       (void)hipEventDestroy(e);
       e = nullptr;
     }
+  if (f->ev_order) {
+    (void)hipEventDestroy(f->ev_order);
+    f->ev_order = nullptr;
+  }
+}
+
+static int frame_order(msgs_frame* f, hipStream_t from, hipStream_t to) {
+  if (!f->ev_order) {
+    hipError_t e = hipEventCreateWithFlags(&f->ev_order, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreateWithFlags");
+  }
+  hipError_t e = hipEventRecord(f->ev_order, from);
+  if (e == hipSuccess) e = hipStreamWaitEvent(to, f->ev_order, 0);
+  return e == hipSuccess ? MSGS_OK : hip_fail(e, "stream ordering of a frame");
+}
+
+int frame_order_before(msgs_frame* f, hipStream_t st) {
+  return st == f->st ? MSGS_OK : frame_order(f, f->st, st);
+}
+
+int frame_order_after(msgs_frame* f, hipStream_t st) {
+  return st == f->st ? MSGS_OK : frame_order(f, st, f->st);
 }
 
 void mark(msgs_frame* f, int i) {
@@ -116,17 +146,14 @@ int radix_passes(int begin_bit, int end_bit) { return end_bit > begin_bit ? (end
 
 // Phase 1 of a render: projection, selection, compaction, depth sort, tile
 // counts.  Leaves the instance total in f->ctr[3] (device); no host sync.
-int render_phase1(msgs_frame* f) {
+// Buffers: those the frame keeps (for blending, the backward and the getters)
+// and the phase's temporaries.
+void phase1_layout(msgs_frame* f, Carve& keep, Carve& tmp) {
   const int64_t n = f->n;
   const ViewParams& v = f->v;
-  hipStream_t st = f->st;
   const int64_t P = (int64_t)v.W * v.H;
   const int ntile = v.Tx * v.Ty;
   const int64_t nb = (n + kBlock - 1) / kBlock;
-  // the depth sort makes 4 passes and ends in its input buffers
-  const bool even = radix_passes(0, 32) % 2 == 0;
-  uint32_t* dv0 = nullptr;
-  Carve keep;
   keep.add(&f->ctr, (8 + kSlotW * kCtrSlots) * sizeof(unsigned long long));
   keep.add(&f->sel, n);
   keep.add(&f->count, n * 4);
@@ -140,44 +167,77 @@ int render_phase1(msgs_frame* f) {
   keep.add(&f->n_last, P * 4);
   keep.add(&f->order, n * 4);
   keep.add(&f->off_d, n * 4);
-  Carve tmp;
   tmp.add(&f->blk_vis, nb * 4);
+  if (nb > kCompactInKernelBlocks) {
+    tmp.add(&f->blk_pre, nb * 4);
+    tmp.add(&f->cscan_tmp, scan_tmp_bytes(nb));
+  }
   tmp.add(&f->dkeys[0], n * 4);
   tmp.add(&f->dkeys[1], n * 4);
   tmp.add(&f->dvals_alt, n * 4);
   tmp.add(&f->scan_tmp2, scan_tmp_bytes(n));
   tmp.add(&f->sort_tmp, radix_tmp_bytes(n, radix_passes(0, 32)));
-  int rc = keep.alloc(f->ctx, st);
-  if (rc != MSGS_OK) return rc;
-  f->blocks.push_back(keep.base);
-  rc = tmp.alloc(f->ctx, st);
-  if (rc != MSGS_OK) return rc;
-  f->tmp_block = tmp.base;
+}
+
+void phase1_launch(msgs_frame* f) {
+  const int64_t n = f->n;
+  const ViewParams& v = f->v;
+  hipStream_t st = f->st;
+  const int ntile = v.Tx * v.Ty;
+  const int64_t nb = (n + kBlock - 1) / kBlock;
+  // the depth sort makes 4 passes and ends in its input buffers
+  const bool even = radix_passes(0, 32) % 2 == 0;
   uint32_t* vin = even ? f->order : f->dvals_alt;
   uint32_t* valt = even ? f->dvals_alt : f->order;
-  dv0 = vin;
   // counters and every status word of the phase, cleared by one launch
   ZeroList z;
   z.add(f->ctr, 2 * (8 + kSlotW * kCtrSlots));
   z.add(f->ranges, (int64_t)ntile * 2);  // tiles with no instance keep (0, 0)
   z.add(f->scan_tmp2, scan_zero_words(n));
   z.add(f->sort_tmp, radix_zero_words(n, radix_passes(0, 32)));
+  if (nb > kCompactInKernelBlocks) z.add(f->cscan_tmp, scan_zero_words(nb));
   launch_zero(z, st);
   mark(f, 0);
   launch_project(f->scene->view, v, f->sel, f->count, f->depthkey, f->rec, f->rect, f->blk_vis,
                  f->ctr + 8, st);
-  launch_compact(f->count, f->depthkey, n, f->blk_vis, f->dkeys[0], dv0, &f->ctr[2], st);
+  launch_compact(f->count, f->depthkey, n, f->blk_vis, f->blk_pre, f->cscan_tmp, f->dkeys[0], vin,
+                 &f->ctr[2], st);
   mark(f, 1);
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
   radix_sort_pairs(f->dkeys[0], vin, f->dkeys[1], valt, d_nvis, n, 0, 32, f->sort_tmp, st, true);
   mark(f, 2);
   scan_excl_u32(f->count, f->order, f->off_d, d_nvis, n, &f->ctr[3], f->scan_tmp2, st, true);
   mark(f, 3);
+}
+
+int render_phase1(msgs_frame* f) {
+  Carve keep, tmp;
+  phase1_layout(f, keep, tmp);
+  int rc = keep.alloc(f->ctx, f->st);
+  if (rc != MSGS_OK) return rc;
+  f->blocks.push_back(keep.base);
+  rc = tmp.alloc(f->ctx, f->st);
+  if (rc != MSGS_OK) return rc;
+  f->tmp_block = tmp.base;
+  phase1_launch(f);
   return MSGS_OK;
 }
 
-// Phase 2: emission, tile sort, ranges, blending.  Needs f->n_inst on the host.
-int render_phase2(msgs_frame* f, float* rgb_out) {
+// Phase 2: emission, tile sort, ranges, blending, for f->n_inst instances
+// (the exact count, or the fixed capacity).  The sorted list must end in the
+// kept buffers (ka, va): emission writes into them for an even number of sort
+// passes and into the temporaries (kb, vb) for an odd number.
+void phase2_layout(msgs_frame* f, Carve& keep, Carve& tmp, Phase2Bufs& b) {
+  const int64_t I = f->n_inst;
+  const int bits = tile_bits(f->v.Tx * f->v.Ty);
+  keep.add(&b.ka, I * 4);
+  keep.add(&b.va, I * 4);
+  tmp.add(&b.kb, I * 4);
+  tmp.add(&b.vb, I * 4);
+  tmp.add(&b.stmp, radix_tmp_bytes(I, radix_passes(0, bits)));
+}
+
+void phase2_launch(msgs_frame* f, float* rgb_out, const Phase2Bufs& b) {
   const int64_t n = f->n;
   const ViewParams& v = f->v;
   hipStream_t st = f->st;
@@ -185,29 +245,14 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   const int64_t I = f->n_inst;
   const int bits = tile_bits(ntile);
   const bool even = radix_passes(0, bits) % 2 == 0;
-  // the sorted list must end in the kept block: emit into it for an even
-  // number of passes, into the temporary block for an odd number
-  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
-  void* stmp = nullptr;
-  Carve keep, tmp;
-  keep.add(&ka, I * 4);
-  keep.add(&va, I * 4);
-  tmp.add(&kb, I * 4);
-  tmp.add(&vb, I * 4);
-  tmp.add(&stmp, radix_tmp_bytes(I, radix_passes(0, bits)));
-  int rc = keep.alloc(f->ctx, st);
-  if (rc != MSGS_OK) return rc;
-  f->blocks.push_back(keep.base);
-  rc = tmp.alloc(f->ctx, st);
-  if (rc != MSGS_OK) return rc;
-  uint32_t* k0 = even ? ka : kb;
-  uint32_t* v0 = even ? va : vb;
-  uint32_t* k1 = even ? kb : ka;
-  uint32_t* v1 = even ? vb : va;
+  uint32_t* k0 = even ? b.ka : b.kb;
+  uint32_t* v0 = even ? b.va : b.vb;
+  uint32_t* k1 = even ? b.kb : b.ka;
+  uint32_t* v1 = even ? b.vb : b.va;
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
   // the status words of a look-back tile sort (none for reduce-then-scan)
   ZeroList z;
-  z.add(stmp, radix_zero_words(I, radix_passes(0, bits)));
+  z.add(b.stmp, radix_zero_words(I, radix_passes(0, bits)));
   launch_zero(z, st);
   mark(f, 4);
   // fixed capacity: the instance count stays on the device (ctr[7] = the
@@ -216,19 +261,33 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   launch_emit(f->order, f->off_d, d_nvis, n, f->count, f->rect, v.Tx, k0, v0, f->emit_base,
               f->capacity ? (uint32_t)I : 0xFFFFFFFFu, f->capacity ? f->ctr : nullptr, st);
   mark(f, 5);
-  radix_sort_pairs(k0, v0, k1, v1, d_inst, I, 0, bits, stmp, st, true);
+  radix_sort_pairs(k0, v0, k1, v1, d_inst, I, 0, bits, b.stmp, st, true);
   mark(f, 6);
-  f->tkeys = ka;
-  f->tvals = va;
+  f->tkeys = b.ka;
+  f->tvals = b.va;
   launch_ranges(f->tkeys, d_inst, (uint32_t)I, f->ranges, st);
   mark(f, 7);
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
                f->ctr + 8, st);
   mark(f, 8);
+}
+
+int render_phase2(msgs_frame* f, float* rgb_out) {
+  Carve keep, tmp;
+  Phase2Bufs b;
+  phase2_layout(f, keep, tmp, b);
+  int rc = keep.alloc(f->ctx, f->st);
+  if (rc != MSGS_OK) return rc;
+  f->blocks.push_back(keep.base);
+  rc = tmp.alloc(f->ctx, f->st);
+  if (rc != MSGS_OK) return rc;
+  phase2_launch(f, rgb_out, b);
+  hipStream_t st = f->st;
   f->ctx->cache.free(f->ctx, tmp.base, st);
   f->ctx->cache.free(f->ctx, f->tmp_block, st);
   f->tmp_block = nullptr;
-  f->blk_vis = f->dvals_alt = nullptr;
+  f->blk_vis = f->blk_pre = f->dvals_alt = nullptr;
+  f->cscan_tmp = nullptr;
   f->dkeys[0] = f->dkeys[1] = nullptr;
   f->scan_tmp2 = f->sort_tmp = nullptr;
   return MSGS_OK;
@@ -599,9 +658,10 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   tmp.add(&a.gsum, (size_t)48 * (size_t)n);
   tmp.add(&a.big, (size_t)4 * (size_t)n);
   tmp.add(&a.nbig, 4);
-  int rc = tmp.alloc(c, st);
+  msgs_frame* fm = const_cast<msgs_frame*>(f);
+  int rc = frame_order_before(fm, st);
+  if (rc == MSGS_OK) rc = tmp.alloc(c, st);
   if (rc == MSGS_OK) {
-    msgs_frame* fm = const_cast<msgs_frame*>(f);
     if (fm->profile) (void)hipEventRecord(fm->ev[9], st);
     launch_backward_zero(a, st);
     if (fm->profile) (void)hipEventRecord(fm->ev[12], st);
@@ -615,6 +675,7 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
     e = hipGetLastError();
     if (e != hipSuccess) rc = hip_fail(e, "backward launch");
     c->cache.free(c, tmp.base, st);
+    if (rc == MSGS_OK) rc = frame_order_after(fm, st);
   }
   return rc;
 }
@@ -651,6 +712,10 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
   tmp.add((void**)&gsum, (size_t)48 * (size_t)n * (size_t)nviews);
   tmp.add((void**)&big, (size_t)4 * (size_t)n);
   tmp.add((void**)&nbig, 4);
+  for (int i = 0; i < nviews; ++i) {
+    int rc0 = frame_order_before(const_cast<msgs_frame*>(frames[i]), st);
+    if (rc0 != MSGS_OK) return rc0;
+  }
   int rc = tmp.alloc(c, st);
   if (rc != MSGS_OK) return rc;
   // per view: adjoint compositing and the per-Gaussian partial sums
@@ -697,6 +762,8 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
   e = hipGetLastError();
   if (e != hipSuccess) rc = hip_fail(e, "backward launch");
   c->cache.free(c, tmp.base, st);
+  for (int i = 0; i < nviews && rc == MSGS_OK; ++i)
+    rc = frame_order_after(const_cast<msgs_frame*>(frames[i]), st);
   return rc;
 }
 

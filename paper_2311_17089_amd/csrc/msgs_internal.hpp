@@ -29,9 +29,13 @@ class DeviceCache {
   Impl* impl;
 };
 
-// Several buffers carved out of one allocation (256-byte aligned parts).
+// Several buffers carved out of one allocation (256-byte aligned parts).  The
+// part list is a fixed array, so laying buffers out allocates nothing.
 struct Carve {
-  std::vector<std::pair<void**, size_t>> parts;
+  static constexpr int kMaxParts = 40;
+  std::pair<void**, size_t> parts[kMaxParts];
+  int nparts = 0;
+  bool overflow = false;  // more than kMaxParts parts: alloc/place refuse
   size_t total = 0;
   void* base = nullptr;
   template <typename T>
@@ -40,6 +44,10 @@ struct Carve {
   }
   size_t add(void** slot, size_t bytes);
   int alloc(msgs_context* c, hipStream_t st);
+  // the parts at their offsets from b (memory the caller provides, 256-byte
+  // aligned, at least `total` bytes); no allocation.  Returns MSGS_OK, or
+  // MSGS_E_INVALID when the layout overflowed its part list.
+  int place(void* b);
 };
 }  // namespace msgs
 
@@ -72,6 +80,9 @@ struct msgs_frame {
   bool profile = false;
   hipEvent_t ev[13] = {};
   bool bwd_recorded = false;
+  // orders a backward on another stream after the render and the frame's
+  // release after that backward (created on first use)
+  hipEvent_t ev_order = nullptr;
   // kept for the backward pass and the getters
   unsigned long long* ctr = nullptr;   // [0] selected [1] blends [2] visible [3] instances [4] visits
                                        // [5] evaluations [6] prefiltered [7] instances that fit
@@ -92,6 +103,8 @@ struct msgs_frame {
   // temporaries of the render (one block, released after blending)
   void* tmp_block = nullptr;
   uint32_t* blk_vis = nullptr;
+  uint32_t* blk_pre = nullptr;        // scanned block counts (scenes of many blocks)
+  void* cscan_tmp = nullptr;          // status words of that scan
   uint32_t* dkeys[2] = {nullptr, nullptr};
   uint32_t* dvals_alt = nullptr;
   void* scan_tmp2 = nullptr;
@@ -118,8 +131,29 @@ int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
 
 int make_view(const msgs_camera* cam, const msgs_render_opts* o, int n_levels, ViewParams* v);
+// The two phases of a render, each as a buffer layout (parts added to the
+// Carves, placed by the caller) and its launches on f->st.
+struct Phase2Bufs {
+  uint32_t* ka = nullptr;  // sorted tile keys and values (kept)
+  uint32_t* va = nullptr;
+  uint32_t* kb = nullptr;  // the sort's other buffers
+  uint32_t* vb = nullptr;
+  void* stmp = nullptr;    // the sort's status / count words
+};
+void phase1_layout(msgs_frame* f, Carve& keep, Carve& tmp);
+void phase1_launch(msgs_frame* f);
+void phase2_layout(msgs_frame* f, Carve& keep, Carve& tmp, Phase2Bufs& b);
+void phase2_launch(msgs_frame* f, float* rgb_out, const Phase2Bufs& b);
 int render_phase1(msgs_frame* f);
 int render_phase2(msgs_frame* f, float* rgb_out);
 void frame_free_all(msgs_frame* f);
+// A backward on stream `st` reads the frame's buffers: st waits for the
+// render's work on the frame's stream first (frame_order_before), and the
+// frame's stream waits for the backward afterwards (frame_order_after), so
+// that the release, which returns the buffers on the frame's stream, cannot
+// hand them out while the backward still reads them.  No-ops when st is the
+// frame's stream.
+int frame_order_before(msgs_frame* f, hipStream_t st);
+int frame_order_after(msgs_frame* f, hipStream_t st);
 unsigned long long* pinned_slot();
 }  // namespace msgs

@@ -13,10 +13,14 @@ namespace msgs {
 void launch_project(const SceneView& s, const ViewParams& v, uint8_t* sel, uint32_t* count,
                     uint32_t* depthkey, Rec* rec, uint2* rect, uint32_t* blk_vis,
                     unsigned long long* slots, hipStream_t st);
-// *total (device u64) receives the number of drawable Gaussians
+// *total (device u64) receives the number of drawable Gaussians.  Above
+// kCompactInKernelBlocks projection blocks the block counts are scanned first
+// into blk_pre (nb words) with scan_tmp (scan_tmp_bytes(nb), its first
+// scan_zero_words(nb) words cleared by the caller); below it both may be null.
+constexpr int64_t kCompactInKernelBlocks = 4096;
 void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
-                    const uint32_t* blk_vis, uint32_t* keys, uint32_t* vals,
-                    unsigned long long* total, hipStream_t st);
+                    const uint32_t* blk_vis, uint32_t* blk_pre, void* scan_tmp, uint32_t* keys,
+                    uint32_t* vals, unsigned long long* total, hipStream_t st);
 // ctr_fit (fixed-capacity renders, else null): ctr_fit[7] = min(ctr_fit[3], cap)
 void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_nvis,
                  int64_t nmax, const uint32_t* count, const uint2* rect, int Tx, uint32_t* tkeys,

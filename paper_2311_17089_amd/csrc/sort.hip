@@ -136,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_lb(const uint32_t* in, const ui
   if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
   __syncthreads();
   const int64_t t = s_tile;
-  const int64_t n = d_n ? (int64_t)*d_n : nmax;
+  const int64_t n = d_n ? min((int64_t)*d_n, nmax) : nmax;
   const int64_t base = t * kScanTile;
   // tiles past the last input element only zero their outputs: they publish
   // no status (no live tile looks back that far) and take no look-back
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_os_hist(const uint32_t* keys, const 
   for (int p = 0; p < 4; ++p)
     for (int w = 0; w < kBlock / 64; ++w) h[p][w][threadIdx.x] = 0;
   __syncthreads();
-  const int64_t n = d_n ? (int64_t)*d_n : nmax;
+  const int64_t n = d_n ? min((int64_t)*d_n, nmax) : nmax;
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * chunk;
   const int64_t i1 = min(n, i0 + chunk);
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_count(const uint32_t* keys, const
   constexpr int kSub = kBlock / 16;
   __shared__ uint32_t h[kSub][kRadix];
   const int sub = ((threadIdx.x >> 6) << 2) | (threadIdx.x & 3);
-  const int64_t n = d_n ? (int64_t)*d_n : nmax;
+  const int64_t n = d_n ? min((int64_t)*d_n, nmax) : nmax;
   const int64_t t = blockIdx.x;
   const int64_t tbase = t * TILE;
   if (tbase >= n) return;
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_rowscan(const uint32_t* counts, u
                                                        uint32_t* rowtot, const uint32_t* d_n,
                                                        int64_t nmax, int tile, int64_t nblk) {
   __shared__ uint32_t wtot[kBlock / 64];
-  const int64_t n = d_n ? (int64_t)*d_n : nmax;
+  const int64_t n = d_n ? min((int64_t)*d_n, nmax) : nmax;
   const int64_t nt = (n + tile - 1) / tile;
   const uint32_t* row = counts + (int64_t)blockIdx.x * nblk;
   uint32_t* out = starts + (int64_t)blockIdx.x * nblk;
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   for (int w = 0; w < kBlock / 64; ++w) cnt[w][threadIdx.x] = 0;
   __syncthreads();
   const int64_t t = RTS ? (int64_t)blockIdx.x : s_tile;
-  const int64_t n = d_n ? (int64_t)*d_n : nmax;
+  const int64_t n = d_n ? min((int64_t)*d_n, nmax) : nmax;
   const int64_t tbase = t * TILE;
   // a tile past the input has nothing to move, and no tile that has items
   // looks back at it (tickets are taken in order)

@@ -66,3 +66,46 @@ def screen_cov64(cam, mu, scale, quat, downscale=1):
         Jac[:, i] = (pinhole64(cam, np.asarray(mu) + e, downscale)
                      - pinhole64(cam, np.asarray(mu) - e, downscale)) / (2 * h)
     return Jac @ Sig @ Jac.T
+
+
+def expected_tile_counts(p, Tx, Ty):
+    """Per-tile number of drawable Gaussians whose tile rectangle covers the
+    tile, from the oracle's projection (2-D difference array over the
+    rectangles, no sort)."""
+    live = np.nonzero(p["ntiles"] > 0)[0]
+    x0, x1, y0, y1 = (p["rect"][i, live].astype(np.int64) for i in range(4))
+    diff = np.zeros((Ty + 1, Tx + 1), np.int64)
+    np.add.at(diff, (y0, x0), 1)
+    np.add.at(diff, (y0, x1 + 1), -1)
+    np.add.at(diff, (y1 + 1, x0), -1)
+    np.add.at(diff, (y1 + 1, x1 + 1), 1)
+    return diff.cumsum(0).cumsum(1)[:Ty, :Tx].ravel()
+
+
+def assert_keys_match_oracle_definition(kg, vg, p, Tx, chunk=1 << 24):
+    """The sorted (tile, depth) list kg/vg against the oracle's definition
+    without sorting it on the CPU: (1) every drawable Gaussian k appears
+    exactly ntiles[k] times; (2) every instance's tile lies in its Gaussian's
+    rectangle and its low 32 bits are the oracle's depth bits of k; (3) the
+    list is strictly increasing in (key, k).  (3) rules out a repeated
+    (tile, k) pair, so with (1) and (2) the instances of k are exactly the
+    tiles of its rectangle; (3) then fixes their order as the stable sort of
+    the emission order.  So the list equals the oracle's keys element by
+    element."""
+    n = p["ntiles"].size
+    assert kg.size == vg.size == int(p["ntiles"].sum())
+    np.testing.assert_array_equal(np.bincount(vg, minlength=n), p["ntiles"])
+    depth_bits = p["depth"].view(np.uint32)
+    for a in range(0, kg.size, chunk):
+        b = min(kg.size, a + chunk)
+        k, v = kg[a:b], vg[a:b]
+        tile = (k >> np.uint64(32)).astype(np.int64)
+        tx, ty = tile % Tx, tile // Tx
+        r = p["rect"][:, v]
+        assert np.all((tx >= r[0]) & (tx <= r[1]) & (ty >= r[2]) & (ty <= r[3]))
+        np.testing.assert_array_equal((k & np.uint64(0xFFFFFFFF)).astype(np.uint32),
+                                      depth_bits[v])
+        e = min(kg.size, b + 1)
+        k2, v2 = kg[a:e], vg[a:e]
+        inc = (k2[1:] > k2[:-1]) | ((k2[1:] == k2[:-1]) & (v2[1:] > v2[:-1]))
+        assert np.all(inc)

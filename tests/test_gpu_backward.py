@@ -142,3 +142,51 @@ def test_autograd_function_matches_direct_backward(ctx):
     direct = _gpu_grads(ctx, sc, cam, 1, Gw)
     for k in GROUPS:
         np.testing.assert_allclose(params[k].grad.cpu().numpy(), direct[k], rtol=1e-6, atol=1e-12)
+
+
+def test_backward_on_another_stream_then_immediate_release(ctx):
+    # render on stream A, backward on stream B, release at once, then render
+    # other views on stream C (whose frames take the released blocks from the
+    # context's cache): the gradients equal those of the same-stream call
+    sc = G.make_scene([20000, 5000, 1200], 71, 3, [-3.8, -2.6, -1.6], sh_std=0.25)
+    sc = O.calibrate(sc, G.calibration_cameras(1071, 320, 240, 330.0))
+    cam = G.lookat_camera(G.sphere_poses(1, 71, 2.6, 3.2)[0], 320, 240, 330.0)
+    others = [G.lookat_camera(p, 320, 240, 330.0) for p in G.sphere_poses(6, 72, 2.4, 3.4)]
+    dsc = M.DeviceScene(ctx, sc)
+    dl = torch.from_numpy(np.random.default_rng(71).standard_normal((240, 320, 3))
+                          .astype(np.float32)).cuda()
+    _, fr = M.render(ctx, dsc, cam, keep_frame=True)
+    ref = {k: v.cpu().numpy() for k, v in M.render_backward(ctx, fr, dl).items()}
+    fr.release()
+    torch.cuda.synchronize()
+    sa, sb, sc_ = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(sa):
+            _, fr = M.render(ctx, dsc, cam, keep_frame=True, stream=sa)
+        with torch.cuda.stream(sb):
+            # the gradient planes and dL/dRGB are ordered by stream B only
+            sb.wait_stream(torch.cuda.current_stream())
+            g = M.render_backward(ctx, fr, dl, stream=sb)
+        fr.release()
+        with torch.cuda.stream(sc_):
+            for o in others:
+                M.render(ctx, dsc, o, stream=sc_)
+        torch.cuda.synchronize()
+        for k in GROUPS:
+            np.testing.assert_array_equal(g[k].cpu().numpy(), ref[k], err_msg=f"{k} rep {rep}")
+    # the multi-view backward on another stream, released at once
+    with torch.cuda.stream(sa):
+        _, f1 = M.render(ctx, dsc, cam, keep_frame=True, stream=sa)
+        _, f2 = M.render(ctx, dsc, cam, keep_frame=True, stream=sa)
+    with torch.cuda.stream(sb):
+        gv = M.render_backward_views(ctx, [f1, f2], [dl, dl], stream=sb)
+    f1.release()
+    f2.release()
+    with torch.cuda.stream(sc_):
+        for o in others:
+            M.render(ctx, dsc, o, stream=sc_)
+    torch.cuda.synchronize()
+    for k in GROUPS:
+        np.testing.assert_array_equal(gv[k].cpu().numpy(), np.float32(ref[k] + ref[k]),
+                                      err_msg=k)
+    dsc.close()

@@ -132,6 +132,71 @@ def test_four_level_full_size_sampled(ctx):
         check_frame(ctx, cal, cam, ds, selective=selective, keys=keys, full_image=False, pix=pix)
 
 
+def test_four_level_single_scale_full_lists(ctx):
+    # the largest tile lists the library builds: the 531,250-Gaussian scene at
+    # 1600x1064 rendered single-scale (every level) at 1x (about 114M tile
+    # instances) and 4x (8.7M).  Masks bit-exact; the whole sorted list against
+    # the oracle's definition (directly against its stable sort at 4x; at 1x by
+    # the counting argument of assert_keys_match_oracle_definition, which needs
+    # no 114M-element CPU sort); ranges from the oracle's per-tile rectangle
+    # counts; 1500 sampled pixels against brute force
+    from _helpers import assert_keys_match_oracle_definition, expected_tile_counts
+    sc = G.four_level_scene()
+    cal = O.calibrate(sc, G.calibration_cameras(1002, 1600, 1064, 1875.0))
+    cam = G.Camera(R=np.eye(3, dtype=np.float32).reshape(9), t=np.array([0, 0, 3], np.float32),
+                   fx=1875.0, fy=1875.0, cx=800.0, cy=532.0, width=1600, height=1064)
+    dsc = M.DeviceScene(ctx, cal)
+    rng = np.random.default_rng(3)
+    for ds in (4, 1):
+        _say(f"  single-scale ds={ds}")
+        W, H = 1600 // ds, 1064 // ds
+        Tx, Ty = (W + 15) // 16, (H + 15) // 16
+        rgb, fr = M.render(ctx, dsc, cam, downscale=ds, selective=False, keep_frame=True)
+        torch.cuda.synchronize()
+        st = fr.stats()
+        p = O.project(cal, cam, downscale=ds, selective=False)
+        np.testing.assert_array_equal(fr.selection(), p["sel"])
+        assert st["n_instances"] == int(p["ntiles"].sum())
+        kg, vg = fr.keys()
+        if ds == 4:
+            ko, vo = O.keys(cal, cam, downscale=ds, selective=False)
+            np.testing.assert_array_equal(kg, ko)
+            np.testing.assert_array_equal(vg, vo)
+        else:
+            assert st["n_instances"] > 100_000_000
+            assert_keys_match_oracle_definition(kg, vg, p, Tx)
+        del kg, vg
+        cnt = expected_tile_counts(p, Tx, Ty)
+        start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+        want = np.stack([np.where(cnt > 0, start, 0), np.where(cnt > 0, start + cnt, 0)], 1)
+        np.testing.assert_array_equal(fr.ranges().astype(np.int64), want)
+        idx = rng.choice(W * H, size=1500, replace=False)
+        pix = np.stack([idx % W, idx // W], 1).astype(np.int32)
+        img = rgb.cpu().numpy()
+        T_g, nc_g = fr.state()
+        r_o, T_o, n_o = O.render_pixels(cal, cam, pix, downscale=ds, selective=False)
+        assert np.abs(img[pix[:, 1], pix[:, 0]] - r_o).max() <= IMG_TOL
+        assert np.abs(T_g[pix[:, 1], pix[:, 0]] - T_o).max() <= IMG_TOL
+        np.testing.assert_array_equal(nc_g[pix[:, 1], pix[:, 0]], n_o)
+        fr.release()
+    dsc.close()
+
+
+def test_non_finite_camera_is_rejected(ctx):
+    import dataclasses
+    sc = G.make_scene([50], 1, 0, [-3.0])
+    dsc = M.DeviceScene(ctx, sc)
+    cam = G.lookat_camera([0, 0, -3], 40, 30, 40.0)
+    R = np.array(cam.R, np.float32).copy()
+    R[4] = np.nan
+    for bad in (dataclasses.replace(cam, cx=float("nan")), dataclasses.replace(cam, fx=float("inf")),
+                dataclasses.replace(cam, R=R)):
+        with pytest.raises(M.MsgsError) as e:
+            M.render(ctx, dsc, bad)
+        assert e.value.code == M.E_INVALID
+    dsc.close()
+
+
 def test_edge_cases(ctx):
     cam = G.lookat_camera([0, 0, -3], 40, 30, 40.0)
     # empty scene

@@ -5,7 +5,9 @@ masked key bits.  Bit-exact: keys and values both.
 Sizes cover the single-pass look-back path (fewer than 512 tiles), the
 reduce-then-scan path (512 tiles and more, with 2048- and 4096-key tiles),
 tile boundaries, ragged tails, heavy key duplication (stability), partial bit
-ranges, and a device-side count smaller than the arrays.
+ranges, 511 tiles (the longest look-back chains) and both sides of the switch
+between the pass kinds, and device-side counts smaller than the arrays or
+larger than them (clamped to the arrays).
 """
 import numpy as np
 import pytest
@@ -42,6 +44,9 @@ def _ref(keys, begin, end, n):
     (2049, 0, 32, 1000),
     (4097, 8, 24, 0),
     (131_071, 0, 32, 0),                # 64 tiles of 2048: look-back
+    (1_046_527, 0, 32, 0),              # 511 tiles: the longest look-back chains
+    (1_046_527, 0, 13, 6700),           # 511 tiles, tile-key shape with duplicates
+    (1_046_528, 0, 32, 0),              # exactly 511 full tiles
     ((1 << 20) - 1, 0, 32, 0),          # 512 tiles of 2048: reduce-then-scan
     (3_000_001, 0, 13, 6700),           # tile-key shape, many duplicates
     (5_000_003, 0, 32, 0),              # 4096-key tiles
@@ -66,7 +71,11 @@ def test_sort_matches_stable_argsort(ctx, n, begin, end, distinct):
     np.testing.assert_array_equal(gv, rv)
 
 
-@pytest.mark.parametrize("nmax,n", [(3_000_000, 2_500_001), (3_000_000, 0), (100_000, 99_999)])
+@pytest.mark.parametrize("nmax,n", [(3_000_000, 2_500_001), (3_000_000, 0), (100_000, 99_999),
+                                     (1_040_000, 1_000_001),   # look-back side of the switch
+                                     (1_060_000, 1_000_001),   # reduce-then-scan side
+                                     (100_000, 150_000),       # count above nmax: clamped
+                                     (2_000_000, 4_000_000)])
 def test_sort_device_count(ctx, nmax, n):
     _say(f"  sort nmax={nmax} device count {n}")
     rng = np.random.default_rng(nmax + n)
@@ -76,6 +85,7 @@ def test_sort_device_count(ctx, nmax, n):
     vt = torch.from_numpy(vals.view(np.int32).copy()).cuda()
     dn = torch.tensor([n], dtype=torch.int32, device="cuda")
     M.debug_sort_pairs(ctx, kt, vt, 0, 32, d_n=dn)
+    n = min(n, nmax)  # a device count above the arrays sorts all of them
     gk = kt.cpu().numpy().view(np.uint32)[:n]
     gv = vt.cpu().numpy().view(np.uint32)[:n]
     rk, rv = _ref(keys, 0, 32, n)

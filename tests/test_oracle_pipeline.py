@@ -376,3 +376,127 @@ def test_render_pixels_matches_full_render():
     np.testing.assert_array_equal(r2, rgb[pix[:, 1], pix[:, 0]])
     np.testing.assert_array_equal(T2, T[pix[:, 1], pix[:, 0]])
     np.testing.assert_array_equal(n2, nc[pix[:, 1], pix[:, 0]])
+
+
+# ------------------------------------------------------------------ tile ranges
+def _tile_keys(tiles, depth_bits=None):
+    t = np.asarray(tiles, np.uint64)
+    d = np.zeros(t.size, np.uint64) if depth_bits is None else np.asarray(depth_bits, np.uint64)
+    return (t << np.uint64(32)) | d
+
+
+def test_tile_ranges_hand_cases():
+    # Sec. 3.1: each tile reads the stretch of the (tile, depth)-sorted list that
+    # holds its id; tiles nobody touches get the empty range (0, 0)
+    np.testing.assert_array_equal(O.tile_ranges(_tile_keys([]), 3), np.zeros((3, 2), np.uint32))
+    np.testing.assert_array_equal(O.tile_ranges(_tile_keys([0, 0, 0]), 1), [[0, 3]])
+    r = O.tile_ranges(_tile_keys([0, 0, 2, 2, 2, 5], [7, 9, 1, 2, 3, 4]), 6)
+    np.testing.assert_array_equal(r, [[0, 2], [0, 0], [2, 5], [0, 0], [0, 0], [5, 6]])
+    # only the last tile of the frame is occupied
+    np.testing.assert_array_equal(O.tile_ranges(_tile_keys([3, 3]), 4),
+                                  [[0, 0], [0, 0], [0, 0], [0, 2]])
+    # only the first tile, with more tiles after it
+    np.testing.assert_array_equal(O.tile_ranges(_tile_keys([0]), 3), [[0, 1], [0, 0], [0, 0]])
+
+
+def test_tile_ranges_position_scan():
+    # brute force: walk the sorted list once; a tile's range opens at the first
+    # position that holds its id and closes one past the last
+    rng = np.random.default_rng(5)
+    for _ in range(25):
+        ntile = int(rng.integers(1, 40))
+        n = int(rng.integers(0, 300))
+        tiles = np.sort(rng.integers(0, ntile, n))
+        keys = np.sort(_tile_keys(tiles, rng.integers(0, 1 << 32, n, dtype=np.uint64)))
+        want = [[0, 0] for _ in range(ntile)]
+        seen = [False] * ntile
+        for i, t in enumerate(tiles.tolist()):
+            if not seen[t]:
+                want[t][0] = i
+                seen[t] = True
+            want[t][1] = i + 1
+        np.testing.assert_array_equal(O.tile_ranges(keys, ntile), np.array(want, np.uint32))
+
+
+def test_tile_ranges_of_a_rendered_frame_cover_each_tile_exactly():
+    # the ranges of a real key list partition it, every range holds only its
+    # tile, and the lengths are the number of Gaussians whose rectangle covers it
+    sc, cam = _random_scene(37)
+    p = O.project(sc, cam)
+    k, _ = O.keys(sc, cam)
+    W, H = O.frame_size(cam, 1)
+    Tx, Ty = (W + 15) // 16, (H + 15) // 16
+    r = O.tile_ranges(k, Tx * Ty).astype(np.int64)
+    tiles = (k >> np.uint64(32)).astype(np.int64)
+    covered = np.zeros(Tx * Ty, np.int64)
+    for g in np.nonzero(p["ntiles"] > 0)[0]:
+        x0, x1, y0, y1 = p["rect"][:, g]
+        for ty in range(y0, y1 + 1):
+            covered[ty * Tx + x0: ty * Tx + x1 + 1] += 1
+    np.testing.assert_array_equal(r[:, 1] - r[:, 0], covered)
+    for t in range(Tx * Ty):
+        assert np.all(tiles[r[t, 0]:r[t, 1]] == t)
+    assert (r[:, 1] - r[:, 0]).sum() == k.size
+
+
+# ------------------------------------------------------------------ non-finite input
+def test_clamp_tile_reading():
+    # the rectangle's float-to-tile conversion clamps to [-1, T] with fmin/fmax
+    # semantics: a NaN operand yields the bound, infinities clamp, truncation
+    assert O.clamp_tile(float("nan"), 7) == -1
+    assert O.clamp_tile(float("inf"), 7) == 7
+    assert O.clamp_tile(float("-inf"), 7) == -1
+    assert O.clamp_tile(1e30, 7) == 7
+    assert O.clamp_tile(3.0, 7) == 3
+    assert O.clamp_tile(-0.0, 7) == 0
+    assert O.clamp_tile(-1.0, 7) == -1
+
+
+@pytest.mark.parametrize("field,value", [("cx", float("nan")), ("fy", float("inf")),
+                                         ("t", float("nan")), ("R", float("-inf"))])
+def test_non_finite_camera_is_rejected(field, value):
+    # with a NaN centre every skip test of the compositing is false, so the
+    # camera itself must be finite; the oracle refuses it like a bad downscale
+    import dataclasses
+    sc = tiny_scene([[0, 0, 4]], [[0.05, 0.05, 0.05]])
+    cam = axis_camera()
+    if field in ("t", "R"):
+        a = np.array(getattr(cam, field), np.float32).copy()
+        a[0] = value
+        bad = dataclasses.replace(cam, **{field: a})
+    else:
+        bad = dataclasses.replace(cam, **{field: value})
+    with pytest.raises(ValueError):
+        O.project(sc, bad)
+    with pytest.raises(ValueError):
+        O.render(sc, bad)
+
+
+def test_counting_key_check_accepts_the_oracle_and_rejects_mutations():
+    # the whole-list check used at full size (no CPU sort of the GPU list):
+    # it accepts the oracle's own sorted keys and rejects a swap, a dropped
+    # instance, a moved tile and a wrong depth
+    from _helpers import assert_keys_match_oracle_definition, expected_tile_counts
+    sc, cam = _random_scene(38)
+    p = O.project(sc, cam)
+    k, v = O.keys(sc, cam)
+    W, H = O.frame_size(cam, 1)
+    Tx, Ty = (W + 15) // 16, (H + 15) // 16
+    assert_keys_match_oracle_definition(k, v, p, Tx, chunk=1000)
+    r = O.tile_ranges(k, Tx * Ty)
+    np.testing.assert_array_equal(r[:, 1] - r[:, 0], expected_tile_counts(p, Tx, Ty))
+    i = int(np.nonzero((k[1:] >> np.uint64(32)) == (k[:-1] >> np.uint64(32)))[0][5])
+    muts = []
+    k1, v1 = k.copy(), v.copy()
+    k1[[i, i + 1]], v1[[i, i + 1]] = k1[[i + 1, i]], v1[[i + 1, i]]
+    muts.append((k1, v1))
+    muts.append((np.delete(k, i), np.delete(v, i)))
+    k3 = k.copy()
+    k3[i] = k3[i] + (np.uint64(1) << np.uint64(32))
+    muts.append((k3, v))
+    k4 = k.copy()
+    k4[i] = k4[i] ^ np.uint64(1)
+    muts.append((k4, v))
+    for km, vm in muts:
+        with pytest.raises(AssertionError):
+            assert_keys_match_oracle_definition(km, vm, p, Tx, chunk=1000)
