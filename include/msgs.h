@@ -206,6 +206,30 @@ int msgs_render(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
                 const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
                 void* stream);
 
+/* Render without allocating: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same render as msgs_render with a fixed tile-list capacity
+ * (no host synchronisation, no frame kept), but every temporary buffer lives
+ * in one device array of MSGS_NOALLOC_SCRATCH_BYTES (256 MiB) that the library
+ * holds on each device it runs on until the process ends; the call itself
+ * calls no hipMalloc, hipFree or other allocating routine.
+ *   opts->instance_capacity  0: as many tile instances as fit in the scratch
+ *                (about (256 MiB - per-Gaussian and per-pixel buffers) / 16
+ *                bytes); > 0: that capacity, MSGS_E_CAPACITY if it does not fit
+ *   counts_out   optional device u64[3]: drawable Gaussians, tile instances the
+ *                frame needs, instances that fit (the image is complete when
+ *                the last two are equal)
+ * Errors: MSGS_E_CAPACITY when the scene (about 90 bytes per Gaussian) and
+ * frame (12 bytes per pixel) buffers do not fit in the scratch, or the
+ * requested capacity does not; MSGS_E_INVALID as msgs_render, and for
+ * profile = 1.  Every call on a device shares that device's scratch and
+ * leaves its contents behind: calls whose work overlaps on one device race and
+ * must be ordered by the caller (e.g. issued on one stream). */
+#define MSGS_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int msgs_render_noalloc(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
+                        const msgs_render_opts* opts, float* rgb_out,
+                        unsigned long long* counts_out, void* stream);
+
 /* Adjoint of msgs_render for the decisions taken in `frame` (selection, tiles,
  * contributor lists, alpha and colour clamps, termination).
  *   dL_drgb  device [H_d][W_d][3] fp32

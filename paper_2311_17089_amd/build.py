@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "libmsgs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["forward.hip", "sort.hip", "backward.hip", "aggregate.hip", "msgs_api.cpp", "alloc.cpp",
-           "server.cpp"]
+           "server.cpp", "noalloc.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
           "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]

@@ -544,6 +544,18 @@ void launch_zero(const ZeroList& z, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(kBlock), 0, st, z, total);
 }
 
+__global__ void k_copy_counts(const unsigned long long* ctr, unsigned long long* out) {
+  if (threadIdx.x == 0) {
+    out[0] = ctr[2];
+    out[1] = ctr[3];
+    out[2] = ctr[7];
+  }
+}
+
+void launch_copy_counts(const unsigned long long* ctr, unsigned long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_counts, dim3(1), dim3(64), 0, st, ctr, out);
+}
+
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kBlock), 0, st, p, n, v);

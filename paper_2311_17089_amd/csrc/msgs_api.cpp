@@ -331,6 +331,8 @@ int msgs_context_create(int device, size_t pool_bytes, msgs_context** out) {
   } else {
     (void)hipGetLastError();
   }
+  int rc = scratch_init(device);
+  if (rc != MSGS_OK) return rc;
   msgs_context* c = new msgs_context();
   c->device = device;
   c->budget = pool_bytes;

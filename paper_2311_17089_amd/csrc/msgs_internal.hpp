@@ -146,6 +146,9 @@ void phase2_layout(msgs_frame* f, Carve& keep, Carve& tmp, Phase2Bufs& b);
 void phase2_launch(msgs_frame* f, float* rgb_out, const Phase2Bufs& b);
 int render_phase1(msgs_frame* f);
 int render_phase2(msgs_frame* f, float* rgb_out);
+// Looks up this device's address of the no-allocation scratch array (the
+// device must be current); once per device, at context creation.
+int scratch_init(int device);
 void frame_free_all(msgs_frame* f);
 // A backward on stream `st` reads the frame's buffers: st waits for the
 // render's work on the frame's stream first (frame_order_before), and the

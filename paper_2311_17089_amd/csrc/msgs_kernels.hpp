@@ -27,6 +27,10 @@ void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_n
                  uint32_t* tvals, uint32_t* emit_base, uint32_t cap, unsigned long long* ctr_fit,
                  hipStream_t st);
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+// out[0] = drawable Gaussians, out[1] = tile instances the frame needs,
+// out[2] = instances that fit its capacity (device u64 each), from a frame's
+// counter block
+void launch_copy_counts(const unsigned long long* ctr, unsigned long long* out, hipStream_t st);
 // Up to kZeroSegs device regions cleared by one launch (the counters, status
 // words and flags that a render or a backward pass needs zeroed up front).
 constexpr int kZeroSegs = 8;

@@ -87,6 +87,8 @@ EXPORTS = {
     "msgs_render": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p], C.c_int),
     "msgs_render_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_render_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p], C.c_int),
     "msgs_debug_sort_pairs": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
                                C.c_int, C.c_void_p], C.c_int),
     "msgs_render_backward_views": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
@@ -297,6 +299,24 @@ def render(ctx: Context, scene: DeviceScene, cam, downscale=1, selective=True,
                             C.byref(fh) if keep_frame else None, C.c_void_p(_stream(stream))))
     if keep_frame:
         return out, Frame(fh, scene, W, H)
+    return out
+
+
+def render_noalloc(ctx: Context, scene: DeviceScene, cam, out: torch.Tensor,
+                   counts: Optional[torch.Tensor] = None, downscale=1, selective=True,
+                   lowpass=0.3, near=0.2, bg=(0.0, 0.0, 0.0), capacity=0, stream=None):
+    """Render into `out` [H_d, W_d, 3] without any device allocation (see
+    msgs_render_noalloc); `counts` (int64 device tensor of 3) receives the
+    drawable Gaussians, the tile instances needed and those that fit."""
+    assert out.is_contiguous() and out.dtype == torch.float32 and out.is_cuda
+    if counts is not None:
+        assert counts.dtype == torch.int64 and counts.numel() >= 3 and counts.is_cuda
+    c = camera_c(cam)
+    o = opts_c(downscale, selective, False, lowpass, near, bg, False, True, capacity)
+    check(lib().msgs_render_noalloc(ctx.h, scene.h, C.byref(c), C.byref(o),
+                                    C.c_void_p(out.data_ptr()),
+                                    C.c_void_p(counts.data_ptr()) if counts is not None else None,
+                                    C.c_void_p(_stream(stream))))
     return out
 
 
