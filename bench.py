@@ -64,6 +64,18 @@ def c2_camera(G):
                     height=H_FULL)
 
 
+def depth_sort_passes(fr):
+    """The depth-sort passes a frame needs: one per 8-bit digit of the 32-bit
+    depth keys of its drawable Gaussians that is not the same for all of them
+    (the library skips the others)."""
+    import numpy as np
+    k, _ = fr.keys()
+    d = np.unique((k & np.uint64(0xFFFFFFFF)).astype(np.uint32))
+    if d.size < 2:
+        return 1
+    return sum(1 for q in range(4) if np.unique((d >> np.uint32(8 * q)) & np.uint32(255)).size > 1)
+
+
 def stage_bytes(st, n, sh_degree, passes_depth, passes_tile):
     """Algorithmic HBM bytes of the memory-bound stages of one render."""
     K = (sh_degree + 1) ** 2
@@ -73,7 +85,9 @@ def stage_bytes(st, n, sh_degree, passes_depth, passes_tile):
         # read mu, s, q, sigma, level, S^max, S^min; write mask and tile count;
         # visible: read SH, write record, rectangle, depth key, compacted pair
         "project": n * (12 + 12 + 16 + 4 + 1 + 4 + 4) + n * (1 + 4) + nv * (12 * K + 48 + 8 + 4 + 8),
-        "depth_sort": passes_depth * nv * (4 + 16),
+        # one read of the keys for the digit histograms, then per pass the keys
+        # and values read and written, except the last pass's keys
+        "depth_sort": nv * 4 + passes_depth * nv * 16 - nv * 4,
         "count_scan": nv * (4 + 4 + 4),
         "emit": nv * (4 + 4 + 8 + 4) + I * 8,
         "tile_sort": passes_tile * I * (4 + 16),
@@ -84,6 +98,57 @@ def stage_bytes(st, n, sh_degree, passes_depth, passes_tile):
         # read the parameters again, write every gradient plane
         "chain_bwd": I // 8 + n * 8 + n * 72 + n * (53 + 12 * K) + n * (44 + 12 * K),
     }
+
+
+def cpu_info():
+    """CPU model (lscpu) and core count of the machine that runs the oracle."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def cpu_baseline_extra():
+    """The oracle at one thread on a smaller sample of the same workload (1024
+    random pixels of the 1x frame and the whole 64x frame), and the oracle's
+    projection + sort stage (projection of all 531,250 Gaussians, emission and
+    std::stable_sort of the 1x frame's tile keys) timed on its own at full size,
+    median of 3."""
+    import numpy as np
+    import oracle as O
+    from paper_2311_17089_amd import scenegen as G
+    sc = G.four_level_scene()
+    cal = O.calibrate(sc, G.calibration_cameras(1002, W_FULL, H_FULL, FOCAL))
+    cam = c2_camera(G)
+    rng = np.random.default_rng(8)
+    idx = rng.choice(W_FULL * H_FULL, size=1024, replace=False)
+    pix = np.stack([idx % W_FULL, idx // W_FULL], 1).astype(np.int32)
+    t0 = time.perf_counter()
+    _, _, nc = O.render_pixels(cal, cam, pix, downscale=1, nthreads=1)
+    _, _, _, b64 = O.render(cal, cam, downscale=64, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    blends1 = int(nc.sum()) + b64
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        k, _ = O.keys(cal, cam, downscale=1)
+        ts.append(time.perf_counter() - t0)
+    tk = sorted(ts)[1]
+    return {"one_thread": {"value": blends1 / dt1, "unit": "blends/s", "cores": 1,
+                           "sample": f"1024 random pixels at 1x and the full 64x frame, "
+                                     f"{blends1} blends in {dt1:.1f} s"},
+            "projection_and_sort_stage": {"ms": tk * 1e3, "instances": int(k.size),
+                                          "instances_per_s": k.size / tk,
+                                          "what": "projection of all Gaussians (OpenMP), tile-key "
+                                                  "emission and one std::stable_sort of the 1x "
+                                                  "frame's keys, median of 3"}}
 
 
 def cpu_baseline(seconds_hint=True):
@@ -248,13 +313,14 @@ def prefilter_effect(M, ctx, dsc, cam, reps=5):
 def training_step(M, G, steps=5, warmup=2):
     """Multi-view training step on the 6M-Gaussian, 5-level scene: 8 views
     (seeded poses on a sphere of radius 2-12), one at each downscale 1, 2, ...,
-    128 of 1920x1080, each rendered with the range update on, then one
-    multi-view backward into one set of gradient planes, all on one stream.
-    dL/dRGB is a fixed seeded tensor per view.  Timed eagerly (exact tile
-    lists, one host synchronisation per view; also with one backward call per
-    view, for comparison) and as one captured HIP graph (fixed tile-list
-    capacities of 1.25x the eager counts, no host synchronisation).
-    Returns step times and blends per second."""
+    128 of 1920x1080, with the range update on, rendered by one multi-view call
+    (one projection pass over the scene for the 8 views), then one multi-view
+    backward into one set of gradient planes, all on one stream.  dL/dRGB is a
+    fixed seeded tensor per view.  Timed eagerly (exact tile lists, one host
+    synchronisation per step; also with one render call per view and one
+    backward call per view, for comparison) and as one captured HIP graph
+    (fixed tile-list capacities of 1.25x the eager counts, no host
+    synchronisation).  Returns step times and blends per second."""
     import numpy as np
     import torch
     ctx = M.Context(0)
@@ -273,18 +339,24 @@ def training_step(M, G, steps=5, warmup=2):
     side.wait_stream(torch.cuda.current_stream())
     caps = [0] * len(views)
 
-    def step(capacity=False, keep=False, batched=True):
-        frames = []
-        if not batched:
-            for k in names:
-                grads[k].copy_(zeros[k])
-        for i, ((cam, d), dl) in enumerate(zip(views, dls)):
-            _, fr = M.render(ctx, dsc, cam, downscale=d, update_range=True, keep_frame=True,
-                             out=outs[i], capacity=caps[i] if capacity else 0)
-            if not batched:
-                M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
-            frames.append(fr)
-        if batched:
+    def step(capacity=False, keep=False, mode="multi"):
+        if mode == "multi":
+            vl = [(cam, {"downscale": d, "update_range": True,
+                         "capacity": caps[i] if capacity else 0})
+                  for i, (cam, d) in enumerate(views)]
+            _, frames = M.render_views(ctx, dsc, vl, keep_frames=True, outs=outs)
+        else:
+            frames = []
+            if mode == "per_view_backward":
+                for k in names:
+                    grads[k].copy_(zeros[k])
+            for i, ((cam, d), dl) in enumerate(zip(views, dls)):
+                _, fr = M.render(ctx, dsc, cam, downscale=d, update_range=True, keep_frame=True,
+                                 out=outs[i], capacity=caps[i] if capacity else 0)
+                if mode == "per_view_backward":
+                    M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
+                frames.append(fr)
+        if mode != "per_view_backward":
             M.render_backward_views(ctx, frames, dls, grads=grads)
         if keep:
             return frames
@@ -305,14 +377,14 @@ def training_step(M, G, steps=5, warmup=2):
             f.release()
         torch.cuda.synchronize()
         t_eager = {}
-        for batched in (False, True):
-            step(batched=batched)
+        for mode in ("per_view_backward", "per_view", "multi"):
+            step(mode=mode)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(steps):
-                step(batched=batched)
+                step(mode=mode)
             torch.cuda.synchronize()
-            t_eager[batched] = (time.perf_counter() - t0) / steps
+            t_eager[mode] = (time.perf_counter() - t0) / steps
         # capture: warm the allocator on this stream with the same capacities
         for _ in range(2):
             step(capacity=True)
@@ -341,11 +413,36 @@ def training_step(M, G, steps=5, warmup=2):
     dsc.close()
     return {"workload": "6M Gaussians over 5 levels (SH degree 3), 8 views at 1920x1080 / "
                         "{1,2,...,128}, range update on, gradients accumulated",
-            "ms_per_step_eager": t_eager[True] * 1e3, "ms_per_step_graph": t_graph * 1e3,
-            "ms_per_step_eager_backward_per_view": t_eager[False] * 1e3,
-            "blends_per_step": blends, "blends_per_s_eager": blends / t_eager[True],
+            "ms_per_step_eager": t_eager["multi"] * 1e3, "ms_per_step_graph": t_graph * 1e3,
+            "ms_per_step_eager_render_per_view": t_eager["per_view"] * 1e3,
+            "ms_per_step_eager_render_and_backward_per_view": t_eager["per_view_backward"] * 1e3,
+            "blends_per_step": blends, "blends_per_s_eager": blends / t_eager["multi"],
             "blends_per_s_graph": blends / t_graph, "steps": steps,
+            "execution": "one multi-view render call (one projection pass for the 8 views) and "
+                         "one multi-view backward per step",
             "graph_capacity_overflows": overflow}
+
+
+def serving_sweep(M, G, rates=(200, 400, 800, 1600, 3200, 6400), n_req=512):
+    """The Poisson replay at increasing offered rates, selective and
+    single-scale: frames/s, p50 and p99 per rate; capacity = the highest
+    frames/s reached; sustainable rate = the highest offered rate served at
+    95% or more of it with p99 at most 50 ms."""
+    out = {}
+    for selective in (True, False):
+        curve = {}
+        for r in rates:
+            res = serving_replay(M, G, n_req=n_req, rate_hz=float(r), selective=selective)
+            curve[str(r)] = {"frames_per_s": res["frames_per_s"], "p50_ms": res["p50_ms"],
+                             "p99_ms": res["p99_ms"], "all_ok": res["all_ok"],
+                             "max_submit_lag_ms": res["max_submit_lag_ms"]}
+        ok = [r for r in rates if curve[str(r)]["frames_per_s"] >= 0.95 * r and
+              curve[str(r)]["p99_ms"] <= 50.0]
+        out["selective" if selective else "single_scale"] = {
+            "by_offered_rate_hz": curve,
+            "capacity_frames_per_s": max(v["frames_per_s"] for v in curve.values()),
+            "sustainable_rate_hz": max(ok) if ok else None}
+    return out
 
 
 def traffic_for(kernel, launch):
@@ -460,10 +557,12 @@ def main():
 
     # counts of one step (deterministic)
     stats = {}
+    dpasses = {}
     for ds in DOWNSCALES:
         _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, profile=True)
         M.render_backward(ctx, fr, dls[ds])
         stats[ds] = fr.stats()
+        dpasses[ds] = depth_sort_passes(fr)
         fr.release()
     blends_per_step = sum(stats[ds]["n_blends"] for ds in DOWNSCALES)
     for ds in DOWNSCALES:
@@ -549,7 +648,7 @@ def main():
     def stage_work(ds):
         st = stats[ds]
         bits = max(1, int(np.ceil(np.log2(max(2, st["tiles_x"] * st["tiles_y"])))))
-        b = stage_bytes(st, sc.n, sc.sh_degree, 4, (bits + 7) // 8)
+        b = stage_bytes(st, sc.n, sc.sh_degree, dpasses[ds], (bits + 7) // 8)
         b["blend"] = FLOPS_PER_VISIT * st["n_visits"] + FLOPS_PER_BLEND * st["n_blends"]
         b["blend_bwd"] = (FLOPS_PER_VISIT * st["n_visits"] +
                           FLOPS_PER_BLEND_BWD * st["n_blends"])
@@ -582,6 +681,12 @@ def main():
         "algorithmic": per + "; visits/blends per launch averaged over the 1x, 4x, 16x, 64x frames",
         "frac_1x_launch": ((work[1][dominant] / (per_ds_stage[1][dominant] * 1e-6)) /
                            ((ALU_PEAK_TFLOPS * 1e12) if alu else (HBM_PEAK_GBS * 1e9))),
+        "frac_by_downscale": {
+            str(ds): round((work[ds][dominant] / (per_ds_stage[ds][dominant] * 1e-6)) /
+                           ((ALU_PEAK_TFLOPS * 1e12) if alu else (HBM_PEAK_GBS * 1e9)), 4)
+            for ds in DOWNSCALES if per_ds_stage[ds][dominant] > 0},
+        "launch_us_by_downscale": {str(ds): round(per_ds_stage[ds][dominant], 2)
+                                   for ds in DOWNSCALES},
         "measured": "HIP events on the frame's stream around each stage, averaged over "
                     f"{args.steps} steps run frame after frame after the timed region",
         "traffic": traffic_for(kname, "avg")})
@@ -649,6 +754,9 @@ def main():
         "ms_per_step_eager": ms_eager,
         "roofline": roof,
         "stage_us_per_step": {s: round(v, 2) for s, v in stage_tot.items()},
+        "stage_us_by_downscale": {str(ds): {s: round(v, 2) for s, v in per_ds_stage[ds].items()}
+                                  for ds in DOWNSCALES},
+        "depth_sort_passes": {str(ds): dpasses[ds] for ds in DOWNSCALES},
         "hbm_stages": hbm_stages,
         "per_downscale": per_ds,
         "prefilter": prefilter_effect(M, ctx, dsc, cam),
@@ -657,7 +765,8 @@ def main():
         print("bench: serving replay (3M-Gaussian scene, 512 requests at 200/s)", file=sys.stderr,
               flush=True)
         out["serving"] = {"selective": serving_replay(M, G, selective=True),
-                          "single_scale": serving_replay(M, G, selective=False)}
+                          "single_scale": serving_replay(M, G, selective=False),
+                          "saturation": serving_sweep(M, G)}
     if not args.no_training:
         print("bench: training step (6M Gaussians, 8 views)", file=sys.stderr, flush=True)
         out["training_step"] = training_step(M, G)
@@ -668,6 +777,8 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"]["cpu"] = cpu_info()
+        out["cpu_baseline"].update(cpu_baseline_extra())
     print(json.dumps(out), flush=True)
     graphs.clear()
     torch.cuda.synchronize()

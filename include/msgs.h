@@ -206,6 +206,24 @@ int msgs_render(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
                 const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
                 void* stream);
 
+/* Render several views of one scene in one call (the views of a serving batch,
+ * or of a multi-scale training step, Sec. 4.1 on multi-scale training and
+ * selective rendering).  The projection, coverage, selection and range update
+ * of up to 8 views run in one pass over the scene that reads each Gaussian's
+ * geometry once; each view's binning, sorts and compositing follow on
+ * `stream`.  Results (images, frames, statistics, and the scene's s_max/s_min
+ * when views update ranges) are bit-identical to msgs_render called on the
+ * views in order.  Views in exact mode (instance_capacity = 0) share one host
+ * synchronisation; with every view in fixed-capacity mode there is none.
+ *   cams, opts  host arrays of nviews entries (opts[i].profile must be 0)
+ *   rgb_out     host array of nviews device pointers, [H_d][W_d][3] fp32 each
+ *   frames_out  optional host array of nviews; receives the frames (release
+ *               each with msgs_frame_release)
+ *   nviews      1..64 (else MSGS_E_INVALID) */
+int msgs_render_views(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cams,
+                      const msgs_render_opts* opts, float* const* rgb_out,
+                      msgs_frame** frames_out, int nviews, void* stream);
+
 /* Render without allocating: for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  The same render as msgs_render with a fixed tile-list capacity
@@ -215,7 +233,9 @@ int msgs_render(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
  * calls no hipMalloc, hipFree or other allocating routine.
  *   opts->instance_capacity  0: as many tile instances as fit in the scratch
  *                (about (256 MiB - per-Gaussian and per-pixel buffers) / 16
- *                bytes); > 0: that capacity, MSGS_E_CAPACITY if it does not fit
+ *                bytes for frames of 128 tiles or more; smaller frames also
+ *                keep replay checkpoints, 64 bytes per instance); > 0: that
+ *                capacity, MSGS_E_CAPACITY if it does not fit
  *   counts_out   optional device u64[3]: drawable Gaussians, tile instances the
  *                frame needs, instances that fit (the image is complete when
  *                the last two are equal)

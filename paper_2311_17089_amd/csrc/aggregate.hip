@@ -10,8 +10,15 @@
 //  (radix sort of the keys, stable: members of a voxel stay in index order)
 //  k_agg_heads   first element of every voxel run.
 //  k_agg_starts  start offset of every run (from the exclusive scan of heads).
-//  k_agg_reduce  one thread per voxel: fp32 sums in sorted order, averages,
-//                enlargement, written to the caller's planar output.
+//  k_agg_invert  sorted position of every chosen Gaussian.
+//  k_agg_pack    every chosen Gaussian, read in index order (coalesced planar
+//                loads), writes its attributes as one row of the sorted table
+//                (position, unit rotation, scale, opacity, SH, coverage), so
+//                that a voxel's members are consecutive rows.
+//  k_agg_reduce  one wave per voxel: lanes sum the voxel's rows (lane l takes
+//                rows l, l + 64, ... in order), a fixed shuffle tree sums the
+//                lanes (deterministic), then averages and enlargement go to
+//                the caller's planar output.
 #include "msgs_device.hpp"
 #include "msgs_kernels.hpp"
 
@@ -99,53 +106,106 @@ __global__ __launch_bounds__(kBlock) void k_agg_starts(const uint32_t* keys, con
   if (i + 1 == n || keys[i + 1] == kAggNone) starts[segidx[i] + heads[i]] = (uint32_t)(i + 1);
 }
 
+__global__ __launch_bounds__(kBlock) void k_agg_invert(const uint32_t* keys, const uint32_t* vals,
+                                                       int64_t n, uint32_t* pos) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n && keys[i] != kAggNone) pos[vals[i]] = (uint32_t)i;
+}
+
+// Row layout of the sorted table: 0..2 position, 3..5 scale, 6..9 unit
+// rotation, 10 opacity, 11 coverage, then the SH planes.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_agg_reduce(SceneView s, const uint32_t* vals,
-                                                       const uint32_t* starts, int64_t nseg,
-                                                       const float* smin, float s_thresh,
+struct AggRow {
+  static constexpr int K3 = 3 * (D + 1) * (D + 1);
+  static constexpr int kVals = 12 + K3;
+  static constexpr int kStride = (kVals + 3) / 4 * 4;  // whole float4s per row
+};
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_agg_pack(SceneView s, const float* smin,
+                                                     float s_thresh, const uint32_t* pos,
+                                                     float* rows) {
+  using Row = AggRow<D>;
+  const int64_t n = s.n;
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k >= n) return;
+  const float cov = smin[k];
+  if (!(cov < s_thresh)) return;
+  float r[Row::kStride];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[a] = s.means[a * n + k];
+    r[3 + a] = s.scales[a * n + k];
+  }
+  const float w = s.quats[k], x = s.quats[n + k], y = s.quats[2 * n + k], z = s.quats[3 * n + k];
+  const float nr = sqrtf(((w * w + x * x) + y * y) + z * z);
+  r[6] = w / nr;
+  r[7] = x / nr;
+  r[8] = y / nr;
+  r[9] = z / nr;
+  r[10] = s.opacity[k];
+  r[11] = cov;
+#pragma unroll
+  for (int i = 0; i < Row::K3; ++i) r[12 + i] = s.sh[(int64_t)i * n + k];
+#pragma unroll
+  for (int i = Row::kVals; i < Row::kStride; ++i) r[i] = 0.0f;
+  float4* dst = (float4*)(rows + (int64_t)pos[k] * Row::kStride);
+#pragma unroll
+  for (int i = 0; i < Row::kStride / 4; ++i)
+    dst[i] = make_float4(r[4 * i], r[4 * i + 1], r[4 * i + 2], r[4 * i + 3]);
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_agg_reduce(const float* rows, const uint32_t* starts,
+                                                       int64_t nseg, float s_thresh,
                                                        float* o_means, float* o_scales,
                                                        float* o_quats, float* o_opacity,
                                                        float* o_sh, int64_t cap) {
-  constexpr int K3 = 3 * (D + 1) * (D + 1);
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= nseg) return;
-  const int64_t n = s.n;
+  using Row = AggRow<D>;
+  const int lane = threadIdx.x & 63;
+  const int64_t j = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;  // one wave per voxel
+  if (j >= nseg) return;  // wave-uniform
   const uint32_t b = starts[j], e = starts[j + 1];
-  float mu[3] = {0.0f, 0.0f, 0.0f}, sc[3] = {0.0f, 0.0f, 0.0f}, q[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  float op = 0.0f, cov = 0.0f;
-  float sh[K3];
+  float acc[Row::kVals];
 #pragma unroll
-  for (int i = 0; i < K3; ++i) sh[i] = 0.0f;
-  for (uint32_t i = b; i < e; ++i) {
-    const int64_t k = vals[i];
+  for (int i = 0; i < Row::kVals; ++i) acc[i] = 0.0f;
+  for (uint32_t t = b + (uint32_t)lane; t < e; t += 64u) {
+    const float4* src = (const float4*)(rows + (int64_t)t * Row::kStride);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      mu[a] = mu[a] + s.means[a * n + k];
-      sc[a] = sc[a] + s.scales[a * n + k];
+    for (int q = 0; q < Row::kStride / 4; ++q) {
+      const float4 v = src[q];
+      if (4 * q + 0 < Row::kVals) acc[4 * q + 0] = acc[4 * q + 0] + v.x;
+      if (4 * q + 1 < Row::kVals) acc[4 * q + 1] = acc[4 * q + 1] + v.y;
+      if (4 * q + 2 < Row::kVals) acc[4 * q + 2] = acc[4 * q + 2] + v.z;
+      if (4 * q + 3 < Row::kVals) acc[4 * q + 3] = acc[4 * q + 3] + v.w;
     }
-    const float w = s.quats[k], x = s.quats[n + k], y = s.quats[2 * n + k], z = s.quats[3 * n + k];
-    const float r = sqrtf(((w * w + x * x) + y * y) + z * z);
-    q[0] = q[0] + w / r;
-    q[1] = q[1] + x / r;
-    q[2] = q[2] + y / r;
-    q[3] = q[3] + z / r;
-    op = op + s.opacity[k];
+  }
+  // lane sums by a fixed butterfly: every lane ends with the same totals
 #pragma unroll
-    for (int i = 0; i < K3; ++i) sh[i] = sh[i] + s.sh[(int64_t)i * n + k];
-    cov = cov + smin[k];
+  for (int i = 0; i < Row::kVals; ++i) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc[i] = acc[i] + __shfl_xor(acc[i], o, 64);
   }
   const float cnt = (float)(e - b);
-  const float grow = s_thresh / (cov / cnt);
+  const float grow = s_thresh / (acc[11] / cnt);
+  // the lanes write the outputs between them
+  for (int i = lane; i < 11 + Row::K3; i += 64) {
+    float v = 0.0f;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    o_means[a * cap + j] = mu[a] / cnt;
-    o_scales[a * cap + j] = (sc[a] / cnt) * grow;
+    for (int q = 0; q < Row::kVals; ++q)
+      if (q == (i < 11 ? i : i + 1)) v = acc[q];
+    if (i < 3) {
+      o_means[i * cap + j] = v / cnt;
+    } else if (i < 6) {
+      o_scales[(i - 3) * cap + j] = (v / cnt) * grow;
+    } else if (i < 10) {
+      o_quats[(i - 6) * cap + j] = v / cnt;
+    } else if (i == 10) {
+      o_opacity[j] = v / cnt;
+    } else {
+      o_sh[(int64_t)(i - 11) * cap + j] = v / cnt;
+    }
   }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) o_quats[a * cap + j] = q[a] / cnt;
-  o_opacity[j] = op / cnt;
-#pragma unroll
-  for (int i = 0; i < K3; ++i) o_sh[(int64_t)i * cap + j] = sh[i] / cnt;
 }
 
 static inline unsigned grid_n(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -170,17 +230,40 @@ void launch_agg_starts(const uint32_t* keys, const uint32_t* heads, const uint32
                      starts);
 }
 
-void launch_agg_reduce(const SceneView& s, const uint32_t* vals, const uint32_t* starts,
-                       int64_t nseg, const float* smin, float s_thresh, float* o_means,
-                       float* o_scales, float* o_quats, float* o_opacity, float* o_sh, int64_t cap,
+size_t agg_row_floats(int sh_degree) {
+  switch (sh_degree) {
+    case 0: return AggRow<0>::kStride;
+    case 1: return AggRow<1>::kStride;
+    case 2: return AggRow<2>::kStride;
+    default: return AggRow<3>::kStride;
+  }
+}
+
+template <int D>
+static void launch_agg_tail_d(const SceneView& s, const uint32_t* keys, const uint32_t* vals,
+                              const uint32_t* starts, int64_t nseg, const float* smin,
+                              float s_thresh, uint32_t* pos, float* rows, float* o_means,
+                              float* o_scales, float* o_quats, float* o_opacity, float* o_sh,
+                              int64_t cap, hipStream_t st) {
+  const int64_t n = s.n;
+  hipLaunchKernelGGL(k_agg_invert, dim3(grid_n(n)), dim3(kBlock), 0, st, keys, vals, n, pos);
+  hipLaunchKernelGGL(k_agg_pack<D>, dim3(grid_n(n)), dim3(kBlock), 0, st, s, smin, s_thresh, pos,
+                     rows);
+  hipLaunchKernelGGL(k_agg_reduce<D>, dim3(grid_n(nseg * 64)), dim3(kBlock), 0, st, rows, starts,
+                     nseg, s_thresh, o_means, o_scales, o_quats, o_opacity, o_sh, cap);
+}
+
+void launch_agg_reduce(const SceneView& s, const uint32_t* keys, const uint32_t* vals,
+                       const uint32_t* starts, int64_t nseg, const float* smin, float s_thresh,
+                       uint32_t* pos, float* rows, float* o_means, float* o_scales,
+                       float* o_quats, float* o_opacity, float* o_sh, int64_t cap,
                        hipStream_t st) {
-  if (nseg == 0) return;
-  const dim3 g(grid_n(nseg)), b(kBlock);
+  if (nseg == 0 || s.n == 0) return;
   switch (s.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_agg_reduce<0>, g, b, 0, st, s, vals, starts, nseg, smin, s_thresh, o_means, o_scales, o_quats, o_opacity, o_sh, cap); break;
-    case 1: hipLaunchKernelGGL(k_agg_reduce<1>, g, b, 0, st, s, vals, starts, nseg, smin, s_thresh, o_means, o_scales, o_quats, o_opacity, o_sh, cap); break;
-    case 2: hipLaunchKernelGGL(k_agg_reduce<2>, g, b, 0, st, s, vals, starts, nseg, smin, s_thresh, o_means, o_scales, o_quats, o_opacity, o_sh, cap); break;
-    default: hipLaunchKernelGGL(k_agg_reduce<3>, g, b, 0, st, s, vals, starts, nseg, smin, s_thresh, o_means, o_scales, o_quats, o_opacity, o_sh, cap); break;
+    case 0: launch_agg_tail_d<0>(s, keys, vals, starts, nseg, smin, s_thresh, pos, rows, o_means, o_scales, o_quats, o_opacity, o_sh, cap, st); break;
+    case 1: launch_agg_tail_d<1>(s, keys, vals, starts, nseg, smin, s_thresh, pos, rows, o_means, o_scales, o_quats, o_opacity, o_sh, cap, st); break;
+    case 2: launch_agg_tail_d<2>(s, keys, vals, starts, nseg, smin, s_thresh, pos, rows, o_means, o_scales, o_quats, o_opacity, o_sh, cap, st); break;
+    default: launch_agg_tail_d<3>(s, keys, vals, starts, nseg, smin, s_thresh, pos, rows, o_means, o_scales, o_quats, o_opacity, o_sh, cap, st); break;
   }
 }
 

@@ -1,8 +1,10 @@
 // Backward pass: the exact adjoint of the forward for its discrete decisions.
 //
-//  k_blend_bwd   one workgroup per tile (XCD-aware order, as the forward).
-//                Each pixel replays its contributors back to front from the
-//                stored final transmittance (T_j = T_{j+1} / (1 - alpha_j)),
+//  k_blend_bwd   one workgroup per tile, or, for frames of few tiles, per
+//                block of 2^lshift positions of the sorted list (one or more
+//                tile segments, see the kernel).  Each pixel replays its
+//                contributors back to front from the stored final (or
+//                block-boundary) transmittance (T_j = T_{j+1} / (1 - alpha_j)),
 //                carrying d . B_j (its dL/dC with the suffix colour B_j, the
 //                only form in which B enters); nine sums per instance (d sigma, d
 //                colour, and the moments of dL/dsigma over the pixel offsets,
@@ -108,60 +110,73 @@ __device__ __forceinline__ float wave_reduce9(const float (&v)[9], int lane) {
 }
 #undef MSGS_DPP
 
-__device__ __forceinline__ int xcd_tile_b(int b, int nblk) {
-  (void)nblk;
+__device__ __forceinline__ int xcd_tile_b(int b) {
   const int c = b >> 3;  // index of the workgroup within its XCD
   return (((c >> 2) << 3) + (b & 7)) * 4 + (c & 3);
 }
 
-__global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const uint32_t* tvals,
-                                                      const Rec* rec, const uint2* rect,
-                                                      const uint32_t* emit_base, ViewParams v,
-                                                      int ntile, const float* T_final,
-                                                      const uint32_t* n_last, const float* dLdC,
-                                                      float* partial, uint32_t* wmask) {
-  __shared__ float4 s0[kBB], s1[kBB], s2[kBB];
-  __shared__ float red[kNP][kBlock / 64][kBB];
-  __shared__ uint8_t lists[4][256];
-  __shared__ uint32_t len[4];
-  __shared__ uint32_t wcnt[4][4];
-  __shared__ uint32_t smax[kBlock / 64];
-  const int tile = xcd_tile_b(blockIdx.x, gridDim.x);
-  if (tile >= ntile) return;
-  const int tx = tile % v.Tx, ty = tile / v.Tx;
+// LDS of one replay workgroup.
+struct BwdShared {
+  float4 s0[kBB], s1[kBB], s2[kBB];
+  float red[kNP][kBlock / 64][kBB];
+  uint8_t lists[4][256];
+  uint32_t len[4];
+  uint32_t wcnt[4][4];
+  uint32_t smax[kBlock / 64];
+};
+
+// Replays the segment [seg0, seg1) of tile `tile`'s list (range rg) back to
+// front for the tile's 256 pixels and writes the partials of its instances.
+// Each pixel starts from T_final and d . B = T_final (d . bg) when its
+// contributors end inside the segment, else from the state the forward stored
+// for position seg1 (ckpt: the transmittance before it and the colour S that
+// the entries from seg1 on add, so d . B = d . S + T_final (d . bg)).
+__device__ __forceinline__ void replay_segment(BwdShared& sh, int tile, uint2 rg, uint32_t seg0,
+                                               uint32_t seg1, const uint32_t* tvals,
+                                               const Rec* rec, const uint2* rect,
+                                               const uint32_t* emit_base, const ViewParams& v,
+                                               const float* T_final, const uint32_t* n_last,
+                                               const float* dLdC, const float4* ckpt,
+                                               int lshift, float* partial, uint32_t* wmask) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tx = tile % v.Tx, ty = tile / v.Tx;
   const int x0 = tx * kTile, y0 = ty * kTile;
   const int px = x0 + (wave & 1) * 8 + (lane & 7);
   const int py = y0 + (wave >> 1) * 8 + (lane >> 3);
   const bool inside = px < v.W && py < v.H;
   const float pcx = (float)px + 0.5f;
   const float pcy = (float)py + 0.5f;
-  const uint2 rg = ranges[tile];
+  const uint32_t e_rel = seg1 - rg.x;  // segment end, relative to the tile
   uint32_t last = 0;
-  float T = 1.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f;
+  float T = 1.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, dB = 0.0f;
   if (inside) {
     const int64_t pix = (int64_t)py * v.W + px;
     last = n_last[pix];
-    T = T_final[pix];
+    const float Tf = T_final[pix];
     d0 = dLdC[pix * 3 + 0];
     d1 = dLdC[pix * 3 + 1];
     d2 = dLdC[pix * 3 + 2];
+    // the suffix colour B (contributions behind the current entry plus the
+    // background seen through them) enters the adjoint only through d . B,
+    // so the replay carries that one scalar, dB += (d . c) w after each entry
+    dB = Tf * ((d0 * v.bg[0] + d1 * v.bg[1]) + d2 * v.bg[2]);
+    T = Tf;
+    if (last > e_rel) {
+      const float4 cp = ckpt[(size_t)(seg1 >> lshift) * (kTile * kTile) + threadIdx.x];
+      T = cp.w;
+      dB = fmaf(d2, cp.z, fmaf(d1, cp.y, fmaf(d0, cp.x, dB)));
+    }
   }
-  // the suffix colour B (contributions behind the current entry plus the
-  // background seen through them) enters the adjoint only through d . B, so
-  // the replay carries that one scalar: dB = d . (T_final bg) at the start,
-  // dB += (d . c) w after each entry
-  float dB = T * ((d0 * v.bg[0] + d1 * v.bg[1]) + d2 * v.bg[2]);
-  // largest contributor count in the tile
-  uint32_t wm = last;
+  // largest contributor count in the tile, capped at the segment's end
+  uint32_t wm = min(last, e_rel);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) wm = max(wm, (uint32_t)__shfl_xor((int)wm, o, 64));
-  if (lane == 0) smax[wave] = wm;
+  if (lane == 0) sh.smax[wave] = wm;
   __syncthreads();
   uint32_t maxlast = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) maxlast = max(maxlast, smax[w]);
-  // batches walk the list back to front (thread t holds position hi - 1 - t);
+  for (int w = 0; w < kBlock / 64; ++w) maxlast = max(maxlast, sh.smax[w]);
+  // batches walk the segment back to front (thread t holds position hi - 1 - t);
   // the gathers of the next batch are in flight while one is replayed
   float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
   uint32_t nslot = 0;
@@ -176,38 +191,38 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
     nslot = emit_base[k] + (uint32_t)((ty - yl) * (xh - xl + 1) + (tx - xl));
   };
   const uint32_t top = rg.x + maxlast;
-  bool have = top > rg.x && threadIdx.x < min((uint32_t)kBB, maxlast);
+  bool have = top > seg0 && threadIdx.x < min((uint32_t)kBB, top - seg0);
   if (have) fetch(top);
-  for (uint32_t hi = top; hi > rg.x;) {
-    const uint32_t lo = hi - rg.x > (uint32_t)kBB ? hi - kBB : rg.x;
+  for (uint32_t hi = top; hi > seg0;) {
+    const uint32_t lo = hi - seg0 > (uint32_t)kBB ? hi - kBB : seg0;
     const int nb = (int)(hi - lo);
     uint32_t qm = 0;
     const uint32_t slot = nslot;
     if (have) {
-      s0[threadIdx.x] = n0;
-      s1[threadIdx.x] = n1;
-      s2[threadIdx.x] = n2;
+      sh.s0[threadIdx.x] = n0;
+      sh.s1[threadIdx.x] = n1;
+      sh.s2[threadIdx.x] = n2;
       qm = quad_mask_exact(n0.x, n0.y, n2.z, n2.w, n0.z, n0.w, n1.x, -n1.z, x0, y0);
       // a quadrant skips the instances at or past its last contributor
       const uint32_t pos_t = hi - 1 - threadIdx.x - rg.x;
 #pragma unroll
       for (int w = 0; w < kBlock / 64; ++w)
-        if (pos_t >= smax[w]) qm &= ~(1u << w);
+        if (pos_t >= sh.smax[w]) qm &= ~(1u << w);
     }
-    build_wave_lists(qm, have, lists, len, wcnt);
-    const uint32_t nlo = lo - rg.x > (uint32_t)kBB ? lo - kBB : rg.x;
-    have = lo > rg.x && (int)threadIdx.x < (int)(lo - nlo);
+    build_wave_lists(qm, have, sh.lists, sh.len, sh.wcnt);
+    const uint32_t nlo = lo - seg0 > (uint32_t)kBB ? lo - kBB : seg0;
+    have = lo > seg0 && (int)threadIdx.x < (int)(lo - nlo);
     if (have) fetch(lo);
-    const int nl = (int)len[wave];
+    const int nl = (int)sh.len[wave];
     for (int i = 0; i < nl; ++i) {
-      const int j = lists[wave][i];
+      const int j = sh.lists[wave][i];
       const uint32_t pos = hi - 1 - (uint32_t)j - rg.x;  // position in the tile list
       // branch-free: every lane evaluates the entry (a wave runs the code
       // whenever one lane needs it); lanes that do not contribute keep T and B
       // and contribute zeros to the sums
-      const float4 a = s0[j];
-      const float4 b = s1[j];
-      const float4 c = s2[j];
+      const float4 a = sh.s0[j];
+      const float4 b = sh.s1[j];
+      const float4 c = sh.s2[j];
       const float dx = pcx - a.x;
       const float dy = pcy - a.y;
       const float qxx = dx * dx, qyy = dy * dy, qxy = dx * dy;
@@ -254,10 +269,10 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
       if (__ballot(contrib)) {
         const float tot = wave_reduce9(g, lane);
         const int q = slot_q(lane & 15);
-        if (lane < 16 && q < kNP) red[q][wave][j] = tot;
+        if (lane < 16 && q < kNP) sh.red[q][wave][j] = tot;
       } else if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < kNP; ++q) red[q][wave][j] = 0.0f;
+        for (int q = 0; q < kNP; ++q) sh.red[q][wave][j] = 0.0f;
       }
     }
     __syncthreads();
@@ -269,14 +284,14 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
         float r = 0.0f;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w)
-          if ((qm >> w) & 1u) r += red[q][w][threadIdx.x];
+          if ((qm >> w) & 1u) r += sh.red[q][w][threadIdx.x];
         sm[q] = r;
         any = any || r != 0.0f;
       }
       if (any) {
         // moments -> d u and d conic: power = -(A11 dx^2 + A22 dy^2)/2 - A12 dx dy
         // with dx = x - u_x, so dpower/du_x = A11 dx + A12 dy and so on
-        const float4 ra = s0[threadIdx.x], rb = s1[threadIdx.x];
+        const float4 ra = sh.s0[threadIdx.x], rb = sh.s1[threadIdx.x];
         const float sg = rb.y;
         const float mx = sm[0], my = sm[1];
         float3* P = (float3*)(partial + (int64_t)slot * kNP);
@@ -289,6 +304,47 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
     }
     __syncthreads();
     hi = lo;
+  }
+}
+
+// BLOCKS = false: one workgroup per tile (XCD-aware order, as the forward),
+// replaying the whole tile list.  BLOCKS = true (frames of few tiles, whose
+// lists are long): one workgroup per block of L = 2^lshift positions of the
+// sorted list, covering the segments of one or more tile lists, replayed one
+// after another from the state the forward stored at block boundaries.  Each
+// instance lies in one tile and one block, so its partials are written once.
+template <bool BLOCKS>
+__global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const uint32_t* tkeys,
+                                                      const uint32_t* tvals, const Rec* rec,
+                                                      const uint2* rect,
+                                                      const uint32_t* emit_base, ViewParams v,
+                                                      int ntile, const float* T_final,
+                                                      const uint32_t* n_last, const float* dLdC,
+                                                      const float4* ckpt, int lshift,
+                                                      const uint32_t* d_inst, uint32_t ninst_max,
+                                                      float* partial, uint32_t* wmask) {
+  __shared__ BwdShared sh;
+  if (!BLOCKS) {
+    const int tile = xcd_tile_b(blockIdx.x);
+    if (tile >= ntile) return;
+    const uint2 rg = ranges[tile];
+    if (rg.y > rg.x)
+      replay_segment(sh, tile, rg, rg.x, rg.y, tvals, rec, rect, emit_base, v, T_final, n_last,
+                     dLdC, ckpt, lshift, partial, wmask);
+    return;
+  }
+  const uint32_t ninst = d_inst ? min(*d_inst, ninst_max) : ninst_max;
+  uint32_t p = (uint32_t)blockIdx.x << lshift;
+  if (p >= ninst) return;
+  const uint32_t pend = min(p + (1u << lshift), ninst);
+  while (p < pend) {  // workgroup-uniform
+    const int tile = (int)tkeys[p];
+    const uint2 rg = ranges[tile];
+    const uint32_t seg1 = min(rg.y, pend);
+    replay_segment(sh, tile, rg, p, seg1, tvals, rec, rect, emit_base, v, T_final, n_last, dLdC,
+                   ckpt, lshift, partial, wmask);
+    p = seg1;
+    __syncthreads();  // the next segment rewrites smax and the LDS batch
   }
 }
 
@@ -651,12 +707,19 @@ void launch_backward_zero(const BwdArgs& a, hipStream_t st) {
 }
 
 void launch_backward_blend(const BwdArgs& a, hipStream_t st) {
+  if (a.n_inst <= 0) return;
   const int ntile = a.v.Tx * a.v.Ty;
-  const int nblk = (ntile + 31) / 32 * 32;
-  if (a.n_inst > 0) {
-    hipLaunchKernelGGL(k_blend_bwd, dim3(nblk), dim3(kBlock), 0, st, a.ranges, a.tvals, a.rec,
-                       a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last, a.dL_drgb, a.partial,
-                       a.wmask);
+  if (a.lshift > 0) {
+    const int64_t nblk = replay_blocks(a.n_inst, a.lshift);
+    hipLaunchKernelGGL(k_blend_bwd<true>, dim3((unsigned)nblk), dim3(kBlock), 0, st, a.ranges,
+                       a.tkeys, a.tvals, a.rec, a.rect, a.emit_base, a.v, ntile, a.T_final,
+                       a.n_last, a.dL_drgb, a.ckpt, a.lshift, a.d_inst, (uint32_t)a.n_inst,
+                       a.partial, a.wmask);
+  } else {
+    const int nblk = (ntile + 31) / 32 * 32;
+    hipLaunchKernelGGL(k_blend_bwd<false>, dim3(nblk), dim3(kBlock), 0, st, a.ranges, a.tkeys,
+                       a.tvals, a.rec, a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last,
+                       a.dL_drgb, a.ckpt, 0, a.d_inst, (uint32_t)a.n_inst, a.partial, a.wmask);
   }
 }
 

@@ -56,18 +56,23 @@ __device__ __forceinline__ bool prefilter_unselected(const ViewParams& v, int n_
   return g1_fails || g2_fails;
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, uint8_t* sel_out,
-                                                    uint32_t* count, uint32_t* depthkey,
-                                                    Rec* rec, uint2* rect, uint32_t* blk_vis,
-                                                    unsigned long long* slots) {
+// Projection of up to kMaxViews views of one scene in one pass: each thread
+// loads its Gaussian's geometry and selection inputs once (one memory round
+// trip), then runs every view in view order.  The view-independent part of
+// the geometry (rotation, 3D covariance) is computed once, when the first
+// view that is not settled by the pre-splat bound needs it.  With a range
+// update, view i selects with the range as views 0 .. i-1 left it (the same
+// values as renders of the views one after another, since each Gaussian's
+// update reads only its own range).  MULTI = false is the single-view kernel.
+template <int D, bool MULTI>
+__global__ __launch_bounds__(kBlock) void k_project(SceneView s, ProjViews pv) {
   const int64_t n = s.n;
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  uint32_t ntiles = 0;
-  int selected = 0;
-  int culled = 0;
+  const int nv = MULTI ? pv.nv : 1;
+  uint32_t drawn = 0, selb = 0, culb = 0;  // bit i: view i
   if (k < n) {
     Geo g;
+    bool shaped = false;
     // every per-Gaussian input of the geometry and the selection, loaded
     // together (one memory round trip; SH follows for the selected only)
     const float sig = s.opacity[k];
@@ -76,95 +81,109 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ViewParams v, u
     const float s0 = s.scales[k], s1 = s.scales[n + k], s2 = s.scales[2 * n + k];
     const float qw = s.quats[k], qx = s.quats[n + k], qy = s.quats[2 * n + k],
                 qz = s.quats[3 * n + k];
-    const float smax = s.s_max[k], smin = s.s_min[k];
+    float smax = s.s_max[k], smin = s.s_min[k];
     const float y255 = 255.0f * sig;
     const bool vis = y255 > 1.0f;
     const float lnq = vis ? log_c(y255) : 0.0f;
-    const bool skip = v.prefilter && v.selective && vis && l != v.update_level &&
-                      prefilter_unselected(v, s.n_levels, mu0, mu1, mu2, s0, s1, s2, smax, smin,
-                                           l, lnq);
-    culled = skip ? 1 : 0;
-    bool front = false;
-    if (!skip) {
-      geo_shape_of(qw, qx, qy, qz, s0, s1, s2, g);
-      front = geo_view(v, mu0, mu1, mu2, g);
-    }
-    float S = 0.0f;
-    bool sel = false;
-    if (front) {
-      S = coverage(g.V11, g.V12, g.V22, vis, lnq);
-      sel = true;
-      if (v.selective) {
-        bool g1 = (l == 0) || (S <= 1.5f * smax);
-        bool g2 = (l == s.n_levels - 1) || (S >= 0.5f * smin) || (S >= 2.0f);
-        sel = g1 && g2;
+    for (int i = 0; i < nv; ++i) {
+      const ViewParams& v = pv.v[i];
+      const ProjOut& o = pv.o[i];
+      uint32_t ntiles = 0;
+      const bool skip = v.prefilter && v.selective && vis && l != v.update_level &&
+                        prefilter_unselected(v, s.n_levels, mu0, mu1, mu2, s0, s1, s2, smax,
+                                             smin, l, lnq);
+      culb |= skip ? 1u << i : 0u;
+      bool front = false;
+      if (!skip) {
+        if (!shaped) {
+          geo_shape_of(qw, qx, qy, qz, s0, s1, s2, g);
+          shaped = true;
+        }
+        front = geo_view(v, mu0, mu1, mu2, g);
       }
-      if (l == v.update_level) {
-        // range update after the selection test has read the old values
-        s.s_max[k] = fmaxf(0.95f * smax, S);
-        s.s_min[k] = fminf(1.05f * smin, S);
-      }
-    }
-    selected = sel ? 1 : 0;
-    sel_out[k] = (uint8_t)selected;
-    if (sel && vis) {
-      float W11 = g.V11 + v.lowpass;
-      float W22 = g.V22 + v.lowpass;
-      float W12 = g.V12;
-      float det2 = W11 * W22 - W12 * W12;
-      if (det2 > 0.0f) {
-        float A11 = W22 / det2;
-        float A12 = -(W12 / det2);
-        float A22 = W11 / det2;
-        float lq = lnq + 0x1p-8f;
-        float ex = sqrtf((2.0f * lq) * W11) * (1.0f + 0x1p-10f) + 0x1p-10f;
-        float ey = sqrtf((2.0f * lq) * W22) * (1.0f + 0x1p-10f) + 0x1p-10f;
-        int xl = max(0, clamp_tile(ceilf(((g.ux - ex) - 15.5f) * 0.0625f), v.Tx));
-        int xh = min(v.Tx - 1, clamp_tile(floorf(((g.ux + ex) - 0.5f) * 0.0625f), v.Tx));
-        int yl = max(0, clamp_tile(ceilf(((g.uy - ey) - 15.5f) * 0.0625f), v.Ty));
-        int yh = min(v.Ty - 1, clamp_tile(floorf(((g.uy + ey) - 0.5f) * 0.0625f), v.Ty));
-        if (xh >= xl && yh >= yl) {
-          ntiles = (uint32_t)(xh - xl + 1) * (uint32_t)(yh - yl + 1);
-          // colour towards the camera centre
-          float d0 = mu0 - v.C[0], d1 = mu1 - v.C[1], d2 = mu2 - v.C[2];
-          float dn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
-          d0 = d0 / dn;
-          d1 = d1 / dn;
-          d2 = d2 / dn;
-          constexpr int K = (D + 1) * (D + 1);
-          float f[K * 3];
-#pragma unroll
-          for (int j = 0; j < K * 3; ++j) f[j] = s.sh[(int64_t)j * n + k];
-          float Y[16];
-          sh_eval(D, d0, d1, d2, Y);
-          float col[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            float acc = 0.5f;
-#pragma unroll
-            for (int j = 0; j < K; ++j) acc = acc + Y[j] * f[j * 3 + c];
-            col[c] = fmaxf(acc, 0.0f);
-          }
-          Rec r;
-          r.r0 = make_float4(g.ux, g.uy, A11, A12);
-          r.r1 = make_float4(A22, sig, -lq, col[0]);
-          r.r2 = make_float4(col[1], col[2], ex, ey);
-          rec[k] = r;
-          rect[k] = make_uint2((uint32_t)xl | ((uint32_t)xh << 16), (uint32_t)yl | ((uint32_t)yh << 16));
-          depthkey[k] = __float_as_uint(g.p[2]);
+      float S = 0.0f;
+      bool sel = false;
+      if (front) {
+        S = coverage(g.V11, g.V12, g.V22, vis, lnq);
+        sel = true;
+        if (v.selective) {
+          bool g1 = (l == 0) || (S <= 1.5f * smax);
+          bool g2 = (l == s.n_levels - 1) || (S >= 0.5f * smin) || (S >= 2.0f);
+          sel = g1 && g2;
+        }
+        if (l == v.update_level) {
+          // range update after the selection test has read the old values
+          smax = fmaxf(0.95f * smax, S);
+          smin = fminf(1.05f * smin, S);
+          s.s_max[k] = smax;
+          s.s_min[k] = smin;
         }
       }
+      selb |= sel ? 1u << i : 0u;
+      o.sel[k] = sel ? (uint8_t)1 : (uint8_t)0;
+      if (sel && vis) {
+        float W11 = g.V11 + v.lowpass;
+        float W22 = g.V22 + v.lowpass;
+        float W12 = g.V12;
+        float det2 = W11 * W22 - W12 * W12;
+        if (det2 > 0.0f) {
+          float A11 = W22 / det2;
+          float A12 = -(W12 / det2);
+          float A22 = W11 / det2;
+          float lq = lnq + 0x1p-8f;
+          float ex = sqrtf((2.0f * lq) * W11) * (1.0f + 0x1p-10f) + 0x1p-10f;
+          float ey = sqrtf((2.0f * lq) * W22) * (1.0f + 0x1p-10f) + 0x1p-10f;
+          int xl = max(0, clamp_tile(ceilf(((g.ux - ex) - 15.5f) * 0.0625f), v.Tx));
+          int xh = min(v.Tx - 1, clamp_tile(floorf(((g.ux + ex) - 0.5f) * 0.0625f), v.Tx));
+          int yl = max(0, clamp_tile(ceilf(((g.uy - ey) - 15.5f) * 0.0625f), v.Ty));
+          int yh = min(v.Ty - 1, clamp_tile(floorf(((g.uy + ey) - 0.5f) * 0.0625f), v.Ty));
+          if (xh >= xl && yh >= yl) {
+            ntiles = (uint32_t)(xh - xl + 1) * (uint32_t)(yh - yl + 1);
+            // colour towards the camera centre
+            float d0 = mu0 - v.C[0], d1 = mu1 - v.C[1], d2 = mu2 - v.C[2];
+            float dn = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
+            d0 = d0 / dn;
+            d1 = d1 / dn;
+            d2 = d2 / dn;
+            constexpr int K = (D + 1) * (D + 1);
+            float f[K * 3];
+#pragma unroll
+            for (int j = 0; j < K * 3; ++j) f[j] = s.sh[(int64_t)j * n + k];
+            float Y[16];
+            sh_eval(D, d0, d1, d2, Y);
+            float col[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              float acc = 0.5f;
+#pragma unroll
+              for (int j = 0; j < K; ++j) acc = acc + Y[j] * f[j * 3 + c];
+              col[c] = fmaxf(acc, 0.0f);
+            }
+            Rec r;
+            r.r0 = make_float4(g.ux, g.uy, A11, A12);
+            r.r1 = make_float4(A22, sig, -lq, col[0]);
+            r.r2 = make_float4(col[1], col[2], ex, ey);
+            o.rec[k] = r;
+            o.rect[k] = make_uint2((uint32_t)xl | ((uint32_t)xh << 16),
+                                   (uint32_t)yl | ((uint32_t)yh << 16));
+            o.depthkey[k] = __float_as_uint(g.p[2]);
+          }
+        }
+      }
+      o.count[k] = ntiles;
+      drawn |= ntiles > 0 ? 1u << i : 0u;
     }
-    count[k] = ntiles;
   }
-  int c = __syncthreads_count(ntiles > 0);
-  int cs = __syncthreads_count(selected);
-  int cc = __syncthreads_count(culled);
-  if (threadIdx.x == 0) {
-    blk_vis[blockIdx.x] = (uint32_t)c;
-    unsigned long long* sl = slots + (blockIdx.x % kCtrSlots) * kSlotW;
-    if (cs) atomicAdd(sl + 0, (unsigned long long)cs);
-    if (cc) atomicAdd(sl + 4, (unsigned long long)cc);
+  for (int i = 0; i < nv; ++i) {
+    const int c = __syncthreads_count((drawn >> i) & 1u);
+    const int cs = __syncthreads_count((selb >> i) & 1u);
+    const int cc = __syncthreads_count((culb >> i) & 1u);
+    if (threadIdx.x == 0) {
+      pv.o[i].blk_vis[blockIdx.x] = (uint32_t)c;
+      unsigned long long* sl = pv.o[i].slots + (blockIdx.x % kCtrSlots) * kSlotW;
+      if (cs) atomicAdd(sl + 0, (unsigned long long)cs);
+      if (cc) atomicAdd(sl + 4, (unsigned long long)cc);
+    }
   }
 }
 
@@ -335,11 +354,25 @@ __device__ __forceinline__ int xcd_quad(int b, int& quad) {
 // into the wave's LDS buffer; then every lane (pixel) composites them.  The
 // next chunk's gathers are in flight meanwhile.  No workgroup barrier: a wave
 // stops as soon as its own 64 pixels are done.
+// For the backward replay, which splits the sorted list into blocks of
+// L = 2^lshift positions, the wave also stores, for every block boundary that
+// falls strictly inside its tile's range, its pixels' transmittance before the
+// boundary and the colour that the entries from the boundary on add (the
+// suffix colour, without the background), at ckpt[(boundary / L) * 256 +
+// pixel in tile].  The colour is accumulated per block (reset at each
+// boundary, where the block's sum joins the running total), and after the tile
+// the wave walks its boundaries back to front adding the block sums: every
+// suffix is a sum of non-negative terms, accurate to its own size, which a
+// difference of two running totals would not be.  Windows of 64 entries are
+// aligned to multiples of 64 in the list so that the boundaries coincide with
+// window starts.  A wave that stops early writes no later boundary: a pixel
+// whose last contributor lies before a boundary never needs the state there.
 __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_t* tvals,
                                                   const Rec* rec, ViewParams v, int ntile,
                                                   float* rgb, float* T_final, uint32_t* n_accum,
                                                   uint32_t* n_last,
-                                                  unsigned long long* slots) {
+                                                  unsigned long long* slots, float4* ckpt,
+                                                  int lshift) {
   __shared__ float4 s0[64], s1[64], s2[64];
   __shared__ uint32_t spos[64];
   int quad;
@@ -357,7 +390,9 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
   const float by0 = (float)qy + 0.5f, by1 = (float)qy + 7.5f;
   const uint2 rg = ranges[tile];
   float T = 1.0f;
-  float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;     // colour of the current block
+  float Cb0 = 0.0f, Cb1 = 0.0f, Cb2 = 0.0f;  // colour of the blocks before it
+  uint32_t nbd = 0, fbd = 0;                 // boundaries stored, the first one's index
   uint32_t cnt = 0, last = 0, wev = 0;
   uint32_t visits = inside ? rg.y - rg.x : 0u;  // replaced by the stop position on termination
   bool done = !inside;
@@ -365,14 +400,28 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
   // gathers of chunk c + 1 are in flight while chunk c is composited (plain
   // float4 registers: an aggregate here would be promoted to LDS)
   float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
-  bool have = rg.x + lane < rg.y;
+  // windows start at multiples of 64 in the list when boundaries are stored
+  const uint32_t cfirst = ckpt ? rg.x & ~63u : rg.x;
+  bool have = cfirst + lane >= rg.x && cfirst + lane < rg.y;
   if (have) {
-    const Rec* rp = rec + tvals[rg.x + lane];
+    const Rec* rp = rec + tvals[cfirst + lane];
     n0 = rp->r0;
     n1 = rp->r1;
     n2 = rp->r2;
   }
-  for (uint32_t c0 = rg.x; c0 < rg.y && __any(!done); c0 += 64) {
+  const uint32_t lmask = (1u << lshift) - 1u;
+  for (uint32_t c0 = cfirst; c0 < rg.y && __any(!done); c0 += 64) {
+    if (ckpt && c0 > rg.x && (c0 & lmask) == 0u) {
+      // the block that ends here: its colour sum (turned into the suffix
+      // colour after the tile) and the transmittance at the boundary
+      ckpt[(size_t)(c0 >> lshift) * (kTile * kTile) + quad * 64 + lane] = make_float4(C0, C1, C2, T);
+      if (nbd == 0) fbd = c0 >> lshift;
+      ++nbd;
+      Cb0 += C0;
+      Cb1 += C1;
+      Cb2 += C2;
+      C0 = C1 = C2 = 0.0f;
+    }
     const bool hit = have && !(n0.x + n2.z < bx0 || n0.x - n2.z > bx1 || n0.y + n2.w < by0 ||
                                n0.y - n2.w > by1) &&
                      level_set_meets_box(n0.x, n0.y, n0.z, n0.w, n1.x, -n1.z, bx0, bx1, by0, by1);
@@ -383,7 +432,7 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
       s0[q] = n0;
       s1[q] = n1;
       s2[q] = n2;
-      spos[q] = c0 - rg.x + (uint32_t)lane + 1;
+      spos[q] = c0 + (uint32_t)lane + 1 - rg.x;
     }
     // the compositing below reads up to three entries past the last hit and
     // masks them out by multiplying with zero, so those entries must hold
@@ -457,12 +506,22 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
   }
   if (inside) {
     const int64_t pix = (int64_t)py * v.W + px;
-    rgb[pix * 3 + 0] = C0 + T * v.bg[0];
-    rgb[pix * 3 + 1] = C1 + T * v.bg[1];
-    rgb[pix * 3 + 2] = C2 + T * v.bg[2];
+    rgb[pix * 3 + 0] = (Cb0 + C0) + T * v.bg[0];
+    rgb[pix * 3 + 1] = (Cb1 + C1) + T * v.bg[1];
+    rgb[pix * 3 + 2] = (Cb2 + C2) + T * v.bg[2];
     T_final[pix] = T;
     n_accum[pix] = cnt;
     n_last[pix] = last;
+  }
+  // block sums -> suffix colours, last boundary first (wave-uniform count)
+  float S0 = C0, S1 = C1, S2 = C2;
+  for (uint32_t m = nbd; m > 0; --m) {
+    float4* cp = ckpt + (size_t)(fbd + m - 1) * (kTile * kTile) + quad * 64 + lane;
+    const float4 o = *cp;
+    *cp = make_float4(S0, S1, S2, o.w);
+    S0 += o.x;
+    S1 += o.y;
+    S2 += o.z;
   }
   // per-wave counts, added to one of kCtrSlots counter slots (atomics on a
   // single address from every wave would serialise at the memory side)
@@ -493,17 +552,23 @@ __global__ __launch_bounds__(kBlock) void k_debug_log(const float* x, float* y, 
 // ------------------------------------------------------------------ launchers
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-void launch_project(const SceneView& s, const ViewParams& v, uint8_t* sel, uint32_t* count,
-                    uint32_t* depthkey, Rec* rec, uint2* rect, uint32_t* blk_vis,
-                    unsigned long long* slots, hipStream_t st) {
-  if (s.n == 0) return;
+template <bool MULTI>
+static void launch_project_t(const SceneView& s, const ProjViews& pv, hipStream_t st) {
   const dim3 g(grid_for(s.n)), b(kBlock);
   switch (s.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project<0>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, slots); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, slots); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, slots); break;
-    default: hipLaunchKernelGGL(k_project<3>, g, b, 0, st, s, v, sel, count, depthkey, rec, rect, blk_vis, slots); break;
+    case 0: hipLaunchKernelGGL((k_project<0, MULTI>), g, b, 0, st, s, pv); break;
+    case 1: hipLaunchKernelGGL((k_project<1, MULTI>), g, b, 0, st, s, pv); break;
+    case 2: hipLaunchKernelGGL((k_project<2, MULTI>), g, b, 0, st, s, pv); break;
+    default: hipLaunchKernelGGL((k_project<3, MULTI>), g, b, 0, st, s, pv); break;
   }
+}
+
+void launch_project(const SceneView& s, const ProjViews& pv, hipStream_t st) {
+  if (s.n == 0 || pv.nv <= 0) return;
+  if (pv.nv == 1)
+    launch_project_t<false>(s, pv, st);
+  else
+    launch_project_t<true>(s, pv, st);
 }
 
 void launch_compact(const uint32_t* count, const uint32_t* depthkey, int64_t n,
@@ -556,6 +621,18 @@ void launch_copy_counts(const unsigned long long* ctr, unsigned long long* out, 
   hipLaunchKernelGGL(k_copy_counts, dim3(1), dim3(64), 0, st, ctr, out);
 }
 
+__global__ void k_gather_counts(CounterList cl, unsigned long long* out) {
+  const int i = threadIdx.x;
+  if (i < cl.n) {
+    out[2 * i] = cl.p[i][2];
+    out[2 * i + 1] = cl.p[i][3];
+  }
+}
+
+void launch_gather_counts(const CounterList& cl, unsigned long long* out, hipStream_t st) {
+  if (cl.n > 0) hipLaunchKernelGGL(k_gather_counts, dim3(1), dim3(64), 0, st, cl, out);
+}
+
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kBlock), 0, st, p, n, v);
@@ -570,11 +647,11 @@ void launch_ranges(const uint32_t* tkeys, const uint32_t* d_n, uint32_t nmax, ui
 
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* slots, hipStream_t st) {
+                  unsigned long long* slots, float4* ckpt, int lshift, hipStream_t st) {
   const int ntile = v.Tx * v.Ty;
   const int nblk = (ntile + 31) / 32 * 32 * 4;
   hipLaunchKernelGGL(k_blend, dim3(nblk), dim3(64), 0, st, ranges, tvals, rec, v, ntile, rgb,
-                     T_final, n_accum, n_last, slots);
+                     T_final, n_accum, n_last, slots, ckpt, lshift);
 }
 
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st) {

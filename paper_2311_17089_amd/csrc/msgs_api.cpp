@@ -174,40 +174,56 @@ void phase1_layout(msgs_frame* f, Carve& keep, Carve& tmp) {
   }
   tmp.add(&f->dkeys[0], n * 4);
   tmp.add(&f->dkeys[1], n * 4);
-  tmp.add(&f->dvals_alt, n * 4);
+  tmp.add(&f->dvals[0], n * 4);
+  tmp.add(&f->dvals[1], n * 4);
   tmp.add(&f->scan_tmp2, scan_tmp_bytes(n));
   tmp.add(&f->sort_tmp, radix_tmp_bytes(n, radix_passes(0, 32)));
 }
 
-void phase1_launch(msgs_frame* f) {
+// The counters and every status word of the first phase, cleared by one launch.
+void phase1_zero(msgs_frame* f) {
   const int64_t n = f->n;
-  const ViewParams& v = f->v;
-  hipStream_t st = f->st;
-  const int ntile = v.Tx * v.Ty;
+  const int ntile = f->v.Tx * f->v.Ty;
   const int64_t nb = (n + kBlock - 1) / kBlock;
-  // the depth sort makes 4 passes and ends in its input buffers
-  const bool even = radix_passes(0, 32) % 2 == 0;
-  uint32_t* vin = even ? f->order : f->dvals_alt;
-  uint32_t* valt = even ? f->dvals_alt : f->order;
-  // counters and every status word of the phase, cleared by one launch
   ZeroList z;
   z.add(f->ctr, 2 * (8 + kSlotW * kCtrSlots));
   z.add(f->ranges, (int64_t)ntile * 2);  // tiles with no instance keep (0, 0)
   z.add(f->scan_tmp2, scan_zero_words(n));
   z.add(f->sort_tmp, radix_zero_words(n, radix_passes(0, 32)));
   if (nb > kCompactInKernelBlocks) z.add(f->cscan_tmp, scan_zero_words(nb));
-  launch_zero(z, st);
-  mark(f, 0);
-  launch_project(f->scene->view, v, f->sel, f->count, f->depthkey, f->rec, f->rect, f->blk_vis,
-                 f->ctr + 8, st);
-  launch_compact(f->count, f->depthkey, n, f->blk_vis, f->blk_pre, f->cscan_tmp, f->dkeys[0], vin,
-                 &f->ctr[2], st);
+  launch_zero(z, f->st);
+}
+
+ProjOut proj_out(msgs_frame* f) {
+  return ProjOut{f->sel, f->count, f->depthkey, f->rec, f->rect, f->blk_vis, f->ctr + 8};
+}
+
+// After the projection: compaction, depth sort, tile-count scan.
+void phase1_tail(msgs_frame* f) {
+  const int64_t n = f->n;
+  hipStream_t st = f->st;
+  launch_compact(f->count, f->depthkey, n, f->blk_vis, f->blk_pre, f->cscan_tmp, f->dkeys[0],
+                 f->dvals[0], &f->ctr[2], st);
   mark(f, 1);
+  // drawable Gaussians in depth order into f->order (depth digits that all
+  // keys share are not sorted)
   const uint32_t* d_nvis = (const uint32_t*)&f->ctr[2];
-  radix_sort_pairs(f->dkeys[0], vin, f->dkeys[1], valt, d_nvis, n, 0, 32, f->sort_tmp, st, true);
+  radix_sort_values(f->dkeys[0], f->dvals[0], f->dkeys[1], f->dvals[1], f->order, d_nvis, n, 0,
+                    32, f->sort_tmp, st, true);
   mark(f, 2);
   scan_excl_u32(f->count, f->order, f->off_d, d_nvis, n, &f->ctr[3], f->scan_tmp2, st, true);
   mark(f, 3);
+}
+
+void phase1_launch(msgs_frame* f) {
+  phase1_zero(f);
+  mark(f, 0);
+  ProjViews pv;
+  pv.nv = 1;
+  pv.v[0] = f->v;
+  pv.o[0] = proj_out(f);
+  launch_project(f->scene->view, pv, f->st);
+  phase1_tail(f);
 }
 
 int render_phase1(msgs_frame* f) {
@@ -230,8 +246,13 @@ int render_phase1(msgs_frame* f) {
 void phase2_layout(msgs_frame* f, Carve& keep, Carve& tmp, Phase2Bufs& b) {
   const int64_t I = f->n_inst;
   const int bits = tile_bits(f->v.Tx * f->v.Ty);
+  f->lshift = replay_block_shift(f->v.Tx * f->v.Ty);
   keep.add(&b.ka, I * 4);
   keep.add(&b.va, I * 4);
+  if (f->lshift > 0)
+    keep.add(&f->ckpt, (size_t)replay_blocks(I, f->lshift) * kTile * kTile * sizeof(float4));
+  else
+    f->ckpt = nullptr;
   tmp.add(&b.kb, I * 4);
   tmp.add(&b.vb, I * 4);
   tmp.add(&b.stmp, radix_tmp_bytes(I, radix_passes(0, bits)));
@@ -268,7 +289,7 @@ void phase2_launch(msgs_frame* f, float* rgb_out, const Phase2Bufs& b) {
   launch_ranges(f->tkeys, d_inst, (uint32_t)I, f->ranges, st);
   mark(f, 7);
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
-               f->ctr + 8, st);
+               f->ctr + 8, f->ckpt, f->lshift, st);
   mark(f, 8);
 }
 
@@ -286,7 +307,7 @@ int render_phase2(msgs_frame* f, float* rgb_out) {
   f->ctx->cache.free(f->ctx, tmp.base, st);
   f->ctx->cache.free(f->ctx, f->tmp_block, st);
   f->tmp_block = nullptr;
-  f->blk_vis = f->blk_pre = f->dvals_alt = nullptr;
+  f->blk_vis = f->blk_pre = f->dvals[0] = f->dvals[1] = nullptr;
   f->cscan_tmp = nullptr;
   f->dkeys[0] = f->dkeys[1] = nullptr;
   f->scan_tmp2 = f->sort_tmp = nullptr;
@@ -498,6 +519,10 @@ int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams
   tmp.add((void**)&segidx, (size_t)n * 4);
   tmp.add((void**)&starts, (size_t)(n + 1) * 4);
   tmp.add((void**)&smin, (size_t)n * 4);
+  uint32_t* pos = nullptr;
+  float* rows = nullptr;
+  tmp.add((void**)&pos, (size_t)n * 4);
+  tmp.add((void**)&rows, (size_t)n * 4 * agg_row_floats(s->view.sh_degree));
   tmp.add((void**)&ctr, 16);
   tmp.add(&ctmp, scan_tmp_bytes(n));
   tmp.add(&stmp, radix_tmp_bytes(n, radix_passes(0, 24)));
@@ -522,8 +547,9 @@ int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams
         rc = fail(MSGS_E_CAPACITY, "aggregation output needs " + std::to_string(nseg) +
                                        " Gaussians, capacity " + std::to_string(out->cap));
       } else {
-        launch_agg_reduce(s->view, sv, starts, (int64_t)nseg, smin, s_thresh, out->means,
-                          out->scales, out->quats, out->opacity, out->sh, out->cap, st);
+        launch_agg_reduce(s->view, sk, sv, starts, (int64_t)nseg, smin, s_thresh, pos, rows,
+                          out->means, out->scales, out->quats, out->opacity, out->sh, out->cap,
+                          st);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(st);
       }
@@ -618,9 +644,156 @@ int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
   *frame_out = f;
   return MSGS_OK;
 }
+// Several views of one scene: one projection pass per kMaxViews views (the
+// geometry read once), then each view's compaction, depth sort and count scan,
+// one host synchronisation for the instance counts of every exact-mode view,
+// and each view's second phase (the views with the fewest instances first).
+int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cams,
+                          const msgs_render_opts* opts, float* const* rgb_out,
+                          msgs_frame** frames_out, int nv, hipStream_t stream,
+                          hipEvent_t* done_ev) {
+  if (!c || !s || !cams || !opts || !rgb_out) return fail(MSGS_E_INVALID, "null argument");
+  if (s->ctx != c) return fail(MSGS_E_INVALID, "scene belongs to another context");
+  if (nv < 1 || nv > kMaxViewsPerCall) return fail(MSGS_E_INVALID, "nviews out of range");
+  std::vector<msgs_frame*> fr((size_t)nv, nullptr);
+  auto free_all = [&]() {
+    for (msgs_frame*& f : fr)
+      if (f) {
+        frame_free_all(f);
+        delete f;
+        f = nullptr;
+      }
+  };
+  bool any_exact = false;
+  for (int i = 0; i < nv; ++i) {
+    const msgs_render_opts& o = opts[i];
+    if (!rgb_out[i]) return fail(MSGS_E_INVALID, "null rgb_out");
+    if (o.profile) return fail(MSGS_E_INVALID, "profiling needs msgs_render");
+    if (o.instance_capacity < 0 || o.instance_capacity >= (1ll << 32))
+      return fail(MSGS_E_INVALID, "instance_capacity must be in [0, 2^32)");
+    ViewParams v;
+    int rc = make_view(&cams[i], &o, s->view.n_levels, &v);
+    if (rc != MSGS_OK) return rc;
+    any_exact = any_exact || o.instance_capacity == 0;
+  }
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  for (int i = 0; i < nv; ++i) {
+    msgs_frame* f = new msgs_frame();
+    fr[(size_t)i] = f;
+    f->capacity = opts[i].instance_capacity;
+    f->ctx = c;
+    f->scene = s;
+    f->st = stream;
+    (void)make_view(&cams[i], &opts[i], s->view.n_levels, &f->v);
+    f->opts = opts[i];
+    f->n = s->view.n;
+    Carve keep, tmp;
+    phase1_layout(f, keep, tmp);
+    int rc = keep.alloc(c, stream);
+    if (rc == MSGS_OK) {
+      f->blocks.push_back(keep.base);
+      rc = tmp.alloc(c, stream);
+      if (rc == MSGS_OK) f->tmp_block = tmp.base;
+    }
+    if (rc != MSGS_OK) {
+      free_all();
+      return rc;
+    }
+  }
+  // instance counts of every view gathered in one device array, read back once
+  unsigned long long* dcounts = nullptr;
+  Carve ctmp;
+  if (any_exact) {
+    ctmp.add(&dcounts, (size_t)nv * 2 * sizeof(unsigned long long));
+    int rc = ctmp.alloc(c, stream);
+    if (rc != MSGS_OK) {
+      free_all();
+      return rc;
+    }
+  }
+  if (t_waiter) t_waiter->on_admitted();
+  for (msgs_frame* f : fr) phase1_zero(f);
+  for (int i0 = 0; i0 < nv; i0 += kMaxViews) {
+    ProjViews pv;
+    pv.nv = std::min(kMaxViews, nv - i0);
+    for (int j = 0; j < pv.nv; ++j) {
+      pv.v[j] = fr[(size_t)(i0 + j)]->v;
+      pv.o[j] = proj_out(fr[(size_t)(i0 + j)]);
+    }
+    launch_project(s->view, pv, stream);
+  }
+  for (msgs_frame* f : fr) phase1_tail(f);
+  int rc = MSGS_OK;
+  if (any_exact) {
+    CounterList cl;
+    cl.n = nv;
+    for (int i = 0; i < nv; ++i) cl.p[i] = fr[(size_t)i]->ctr;
+    launch_gather_counts(cl, dcounts, stream);
+    std::vector<unsigned long long> hc((size_t)nv * 2);
+    e = hipMemcpyAsync(hc.data(), dcounts, hc.size() * sizeof(unsigned long long),
+                       hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) rc = hip_fail(e, "instance count readback");
+    for (int i = 0; i < nv && rc == MSGS_OK; ++i) {
+      msgs_frame* f = fr[(size_t)i];
+      if (f->capacity) continue;
+      f->n_vis = (int64_t)hc[2 * (size_t)i];
+      f->n_inst = (int64_t)hc[2 * (size_t)i + 1];
+      if (hc[2 * (size_t)i + 1] >= (1ull << 32))
+        rc = fail(MSGS_E_CAPACITY, "more than 2^32 tile instances");
+    }
+    c->cache.free(c, ctmp.base, stream);
+  }
+  for (msgs_frame* f : fr)
+    if (f->capacity) {
+      f->n_vis = f->n;
+      f->n_inst = f->capacity;
+    }
+  // second phases, fewest instances first (the views are independent)
+  std::vector<int> ord((size_t)nv);
+  for (int i = 0; i < nv; ++i) ord[(size_t)i] = i;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int a, int b) { return fr[(size_t)a]->n_inst < fr[(size_t)b]->n_inst; });
+  for (int i : ord) {
+    if (rc != MSGS_OK) break;
+    rc = render_phase2(fr[(size_t)i], rgb_out[i]);
+    if (rc == MSGS_OK && done_ev) {
+      e = hipEventRecord(done_ev[i], stream);
+      if (e != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+    }
+  }
+  if (rc == MSGS_OK) {
+    e = hipGetLastError();
+    if (e != hipSuccess) rc = hip_fail(e, "kernel launch");
+  }
+  if (rc != MSGS_OK) {
+    free_all();
+    if (frames_out)
+      for (int i = 0; i < nv; ++i) frames_out[i] = nullptr;
+    return rc;
+  }
+  for (int i = 0; i < nv; ++i) {
+    if (frames_out) {
+      frames_out[i] = fr[(size_t)i];
+    } else {
+      frame_free_all(fr[(size_t)i]);
+      delete fr[(size_t)i];
+    }
+    fr[(size_t)i] = nullptr;
+  }
+  return MSGS_OK;
+}
 }  // namespace msgs
 
 extern "C" {
+
+int msgs_render_views(msgs_context* c, msgs_scene* s, const msgs_camera* cams,
+                      const msgs_render_opts* opts, float* const* rgb_out,
+                      msgs_frame** frames_out, int nviews, void* stream) {
+  return render_views_internal(c, s, cams, opts, rgb_out, frames_out, nviews,
+                               (hipStream_t)stream, nullptr);
+}
 
 int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_drgb,
                          const msgs_grads* out, void* stream) {
@@ -636,7 +809,11 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   a.s = f->scene->view;
   a.v = f->v;
   a.ranges = f->ranges;
+  a.tkeys = f->tkeys;
   a.tvals = f->tvals;
+  a.ckpt = f->ckpt;
+  a.lshift = f->lshift;
+  a.d_inst = f->capacity ? (const uint32_t*)&f->ctr[7] : nullptr;
   a.rec = f->rec;
   a.rect = f->rect;
   a.emit_base = f->emit_base;
@@ -727,7 +904,11 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
     a.s = f->scene->view;
     a.v = f->v;
     a.ranges = f->ranges;
+    a.tkeys = f->tkeys;
     a.tvals = f->tvals;
+    a.ckpt = f->ckpt;
+    a.lshift = f->lshift;
+    a.d_inst = f->capacity ? (const uint32_t*)&f->ctr[7] : nullptr;
     a.rec = f->rec;
     a.rect = f->rect;
     a.emit_base = f->emit_base;

@@ -10,6 +10,7 @@
 
 #include "../../include/msgs.h"
 #include "msgs_device.hpp"
+#include "msgs_kernels.hpp"
 
 namespace msgs {
 // Stream-ordered caching allocator (alloc.cpp).
@@ -98,6 +99,9 @@ struct msgs_frame {
   uint32_t* n_last = nullptr;
   uint32_t* tkeys = nullptr;
   uint32_t* tvals = nullptr;
+  float4* ckpt = nullptr;             // suffix colour and transmittance at every
+                                      // replay-block boundary inside a tile
+  int lshift = 8;                     // replay block length 2^lshift
   uint32_t* order = nullptr;          // drawable Gaussians in depth order
   uint32_t* off_d = nullptr;          // their emission offsets
   // temporaries of the render (one block, released after blending)
@@ -106,7 +110,7 @@ struct msgs_frame {
   uint32_t* blk_pre = nullptr;        // scanned block counts (scenes of many blocks)
   void* cscan_tmp = nullptr;          // status words of that scan
   uint32_t* dkeys[2] = {nullptr, nullptr};
-  uint32_t* dvals_alt = nullptr;
+  uint32_t* dvals[2] = {nullptr, nullptr};
   void* scan_tmp2 = nullptr;
   void* sort_tmp = nullptr;
 };
@@ -126,6 +130,12 @@ constexpr int kRequeue = -100;  // internal: request aborted to break an admissi
 int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
                     const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
                     hipStream_t stream);
+constexpr int kMaxViewsPerCall = 64;
+// done_ev (nullable): nv events, event i recorded after view i's last kernel
+int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cams,
+                          const msgs_render_opts* opts, float* const* rgb_out,
+                          msgs_frame** frames_out, int nv, hipStream_t stream,
+                          hipEvent_t* done_ev);
 extern thread_local std::string t_err;
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
@@ -141,7 +151,10 @@ struct Phase2Bufs {
   void* stmp = nullptr;    // the sort's status / count words
 };
 void phase1_layout(msgs_frame* f, Carve& keep, Carve& tmp);
-void phase1_launch(msgs_frame* f);
+void phase1_launch(msgs_frame* f);  // phase1_zero, the projection of f's view, phase1_tail
+void phase1_zero(msgs_frame* f);
+ProjOut proj_out(msgs_frame* f);
+void phase1_tail(msgs_frame* f);
 void phase2_layout(msgs_frame* f, Carve& keep, Carve& tmp, Phase2Bufs& b);
 void phase2_launch(msgs_frame* f, float* rgb_out, const Phase2Bufs& b);
 int render_phase1(msgs_frame* f);

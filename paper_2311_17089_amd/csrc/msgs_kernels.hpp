@@ -10,9 +10,25 @@
 namespace msgs {
 
 // forward.hip
-void launch_project(const SceneView& s, const ViewParams& v, uint8_t* sel, uint32_t* count,
-                    uint32_t* depthkey, Rec* rec, uint2* rect, uint32_t* blk_vis,
-                    unsigned long long* slots, hipStream_t st);
+// Outputs of the projection for one view (per Gaussian: selection, tile
+// count, depth key, record, rectangle; per block: drawable count; counter slots).
+struct ProjOut {
+  uint8_t* sel;
+  uint32_t* count;
+  uint32_t* depthkey;
+  Rec* rec;
+  uint2* rect;
+  uint32_t* blk_vis;
+  unsigned long long* slots;
+};
+// Views projected together in one pass over the scene.
+constexpr int kMaxViews = 8;
+struct ProjViews {
+  ViewParams v[kMaxViews];
+  ProjOut o[kMaxViews];
+  int nv;
+};
+void launch_project(const SceneView& s, const ProjViews& pv, hipStream_t st);
 // *total (device u64) receives the number of drawable Gaussians.  Above
 // kCompactInKernelBlocks projection blocks the block counts are scanned first
 // into blk_pre (nb words) with scan_tmp (scan_tmp_bytes(nb), its first
@@ -31,6 +47,13 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 // out[2] = instances that fit its capacity (device u64 each), from a frame's
 // counter block
 void launch_copy_counts(const unsigned long long* ctr, unsigned long long* out, hipStream_t st);
+// out[2 i] = drawable Gaussians, out[2 i + 1] = tile instances of frame i, from
+// the counter blocks of up to 64 frames, in one launch
+struct CounterList {
+  const unsigned long long* p[64];
+  int n;
+};
+void launch_gather_counts(const CounterList& cl, unsigned long long* out, hipStream_t st);
 // Up to kZeroSegs device regions cleared by one launch (the counters, status
 // words and flags that a render or a backward pass needs zeroed up front).
 constexpr int kZeroSegs = 8;
@@ -49,9 +72,28 @@ struct ZeroList {
 void launch_zero(const ZeroList& z, hipStream_t st);
 void launch_ranges(const uint32_t* tkeys, const uint32_t* d_n, uint32_t nmax, uint2* ranges,
                    hipStream_t st);
+// ckpt (nullable, with lshift > 0): for every replay-block boundary inside a
+// tile, per pixel the suffix colour from the boundary on and the transmittance
+// before it, for the backward (block length 2^lshift >= 64; see
+// replay_block_shift)
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* slots, hipStream_t st);
+                  unsigned long long* slots, float4* ckpt, int lshift, hipStream_t st);
+// log2 of the backward replay's block length for a frame of ntile tiles, or 0
+// for a replay with one workgroup per tile.  Frames of 128 tiles and more keep
+// one workgroup per tile (enough workgroups, and an XCD-aware tile order whose
+// L2s share the records of neighbouring tiles: measured on a 425-tile frame,
+// 68 us against 84-95 us for blocks of 128-512 positions).  Frames of fewer
+// tiles have long lists that one workgroup per tile replays one entry after
+// another, so their lists are cut into blocks of 64 positions, one workgroup
+// each (35- and 2-tile frames: 60 -> 39 us and 71 -> 24 us).  It depends on
+// the frame's size only, not on its instance count, so that a fixed-capacity
+// render composites exactly as the exact-count render of the same view (the
+// colour is summed per block).
+inline int replay_block_shift(int ntile) { return ntile >= 128 ? 0 : 6; }
+inline int64_t replay_blocks(int64_t n_inst, int lshift) {
+  return lshift > 0 ? (n_inst + ((int64_t)1 << lshift) - 1) >> lshift : 0;
+}
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st);
 void launch_debug_log(const float* x, float* y, int64_t n, hipStream_t st);
 
@@ -73,13 +115,27 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
                      const uint32_t* d_n, int64_t nmax, int begin_bit, int end_bit, void* tmp,
                      hipStream_t st, bool zeroed = false);
 int64_t radix_zero_words(int64_t nmax, int npass);
+// The same stable sort when only the sorted values are needed: they land in
+// vals_final (distinct from vals and vals_alt); keys, vals, keys_alt and
+// vals_alt are overwritten.  Below 512 tiles (the onesweep passes) a pass
+// whose digit is the same for every key is skipped on the device, so a key
+// range narrower than the key type costs fewer passes (the view-space depths
+// of a scene seen from outside often share their exponent and top mantissa
+// bits), with no host decision: the launches stay the same.
+void radix_sort_values(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                       uint32_t* vals_final, const uint32_t* d_n, int64_t nmax, int begin_bit,
+                       int end_bit, void* tmp, hipStream_t st, bool zeroed = false);
 
 // backward.hip
 struct BwdArgs {
   SceneView s;
   ViewParams v;
   const uint2* ranges;
+  const uint32_t* tkeys;    // sorted tile ids (the tile of every list position)
   const uint32_t* tvals;
+  const float4* ckpt;       // suffix colour and transmittance at every replay-block boundary
+  int lshift;               // replay block length 2^lshift
+  const uint32_t* d_inst;   // instances in the list on the device (fixed capacity), or null
   const Rec* rec;
   const uint2* rect;
   const uint32_t* emit_base;
@@ -133,9 +189,13 @@ void launch_agg_cover(const SceneView& s, const ViewParams* views, int ncams, in
 void launch_agg_heads(const uint32_t* keys, int64_t n, uint32_t* heads, hipStream_t st);
 void launch_agg_starts(const uint32_t* keys, const uint32_t* heads, const uint32_t* segidx,
                        int64_t n, uint32_t* starts, hipStream_t st);
-void launch_agg_reduce(const SceneView& s, const uint32_t* vals, const uint32_t* starts,
-                       int64_t nseg, const float* smin, float s_thresh, float* o_means,
-                       float* o_scales, float* o_quats, float* o_opacity, float* o_sh, int64_t cap,
+// floats per row of the sorted attribute table (pos: n words, rows: n rows)
+size_t agg_row_floats(int sh_degree);
+// keys/vals: the voxel-sorted (key, index) pairs; starts: nseg + 1 run starts
+void launch_agg_reduce(const SceneView& s, const uint32_t* keys, const uint32_t* vals,
+                       const uint32_t* starts, int64_t nseg, const float* smin, float s_thresh,
+                       uint32_t* pos, float* rows, float* o_means, float* o_scales,
+                       float* o_quats, float* o_opacity, float* o_sh, int64_t cap,
                        hipStream_t st);
 
 }  // namespace msgs

@@ -104,11 +104,15 @@ extern "C" int msgs_render_noalloc(msgs_context* c, msgs_scene* s, const msgs_ca
   int64_t I = o.instance_capacity;
   if (I == 0) {
     // as many tile instances as fit: 16 bytes each (keys and values, two
-    // buffers) plus the sort's per-tile words
-    I = std::min<int64_t>((int64_t)((cap_bytes - fixed) / 16), 0xFFFFFFFFll);
+    // buffers), the replay checkpoints (256 pixels x 16 bytes per block of
+    // 2^lshift instances) and the sort's per-tile words
+    const int lshift = replay_block_shift(v.Tx * v.Ty);
+    const double per_inst =
+        16.0 + (lshift > 0 ? (double)(kTile * kTile * 16) / (double)(1ll << lshift) : 0.0);
+    I = std::min<int64_t>((int64_t)((double)(cap_bytes - fixed) / per_inst), 0xFFFFFFFFll);
     for (size_t need = noalloc_bytes(f, I); I > 0 && need > cap_bytes;
          need = noalloc_bytes(f, I))
-      I -= std::max<int64_t>(1, (int64_t)((need - cap_bytes + 15) / 16));
+      I -= std::max<int64_t>(1, (int64_t)((double)(need - cap_bytes) / per_inst) + 1);
     if (I <= 0) return fail(MSGS_E_CAPACITY, "no room for tile instances in the scratch");
   } else {
     const size_t need = noalloc_bytes(f, I);

@@ -1,17 +1,26 @@
 // Continuous-batching render server over one resident scene.
 //
 // Requests (camera, options, caller-owned output) enter a FIFO queue.  A fixed
-// set of slots, each a host worker thread with its own HIP stream, take the
-// oldest request as soon as the slot is free; the frames of different slots run
-// concurrently on the device.  Device memory is the admission criterion: every
-// frame allocates from the context's budget (per-Gaussian buffers first, then,
-// once the tile-instance count is known, the tile lists).  A request whose
-// allocation does not fit waits until another request completes and returns its
-// memory.  If every in-flight request is waiting, all but the oldest give their
-// memory back and return to the head of the queue, so the oldest always makes
-// progress; a request that cannot fit even alone completes with MSGS_E_NOMEM.
+// set of slots, each a host worker thread with its own HIP stream, take work
+// as soon as the slot is free: the oldest request and the requests queued
+// behind it, up to kServerBatch, as one batch.  A batch is rendered by one
+// multi-view call: one projection pass over the resident scene for all its
+// views (the geometry read once), one host synchronisation for the instance
+// counts, then each view's binning, sorts and compositing, the views with the
+// fewest instances first; each request completes when its own last kernel
+// does.  Under light load batches hold one request; as the queue grows they
+// fill up, and the frames of different slots run concurrently on the device.
+// Device memory is the admission criterion: every frame allocates from the
+// context's budget (per-Gaussian buffers first, then, once the tile-instance
+// count is known, the tile lists).  A batch whose allocation does not fit waits
+// until another batch completes and returns its memory.  If every in-flight
+// batch is waiting, all but the oldest give their memory back and return to the
+// head of the queue, so the oldest always makes progress; a batch that cannot
+// fit alone returns all but its first request to the queue and retries that
+// one alone, which completes with MSGS_E_NOMEM if it still does not fit.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -39,11 +48,14 @@ struct Request {
 
 }  // namespace
 
+constexpr int kServerBatch = 8;  // requests per multi-view call (one projection pass)
+
 struct msgs_server {
   msgs_context* ctx = nullptr;
   msgs_scene* scene = nullptr;
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;  // kServerBatch per slot: completion of each view
   std::mutex mu;
   std::condition_variable cv_queue, cv_done, cv_mem;
   std::deque<Request> queue;
@@ -97,50 +109,99 @@ struct Waiter final : AdmitWaiter {
 void worker_loop(msgs_server* s, int slot) {
   (void)hipSetDevice(s->ctx->device);
   hipStream_t st = s->streams[slot];
+  hipEvent_t* evs = &s->events[(size_t)slot * kServerBatch];
   for (;;) {
-    Request rq;
+    std::vector<Request> batch;
     {
       std::unique_lock<std::mutex> g(s->mu);
       s->cv_queue.wait(g, [&] { return s->stop || !s->queue.empty(); });
       if (s->stop) return;  // queued requests are dropped
-      rq = s->queue.front();
-      s->queue.pop_front();
-      s->active_seq.push_back(rq.seq);
+      while (!s->queue.empty() && (int)batch.size() < kServerBatch) {
+        batch.push_back(s->queue.front());
+        s->queue.pop_front();
+      }
+      s->active_seq.push_back(batch[0].seq);  // a batch is one admission unit
     }
     const double t_take = s->now_us();
-    Waiter w(s, rq.seq);
-    t_waiter = &w;
-    msgs_frame* fr = nullptr;
-    int rc = render_internal(s->ctx, s->scene, &rq.cam, &rq.opts, rq.rgb, &fr, st);
-    t_waiter = nullptr;
-    int64_t blends = 0;
-    if (rc == MSGS_OK) {
-      msgs_stats stt;
-      rc = msgs_frame_stats(fr, &stt);  // synchronises the slot's stream
-      blends = stt.n_blends;
+    int rc = MSGS_OK;
+    Waiter w(s, batch[0].seq);
+    std::vector<msgs_frame*> frames;
+    for (;;) {
+      const int nb = (int)batch.size();
+      std::vector<msgs_camera> cams((size_t)nb);
+      std::vector<msgs_render_opts> opts((size_t)nb);
+      std::vector<float*> rgbs((size_t)nb);
+      for (int i = 0; i < nb; ++i) {
+        cams[(size_t)i] = batch[(size_t)i].cam;
+        opts[(size_t)i] = batch[(size_t)i].opts;
+        rgbs[(size_t)i] = batch[(size_t)i].rgb;
+      }
+      frames.assign((size_t)nb, nullptr);
+      t_waiter = &w;
+      rc = render_views_internal(s->ctx, s->scene, cams.data(), opts.data(), rgbs.data(),
+                                 frames.data(), nb, st, evs);
+      t_waiter = nullptr;
+      if (rc != MSGS_E_NOMEM || nb == 1) break;
+      // the batch does not fit: the rest goes back to the head of the queue
+      // (in order) and the first request is tried alone
+      {
+        std::lock_guard<std::mutex> g(s->mu);
+        for (int i = nb - 1; i >= 1; --i) s->queue.push_front(batch[(size_t)i]);
+      }
+      s->cv_queue.notify_one();
+      batch.resize(1);
     }
-    if (fr) msgs_frame_release(fr);
-    const double t_done = s->now_us();
+    const int nb = (int)batch.size();
+    std::vector<double> t_done((size_t)nb, 0.0);
+    std::vector<int> status((size_t)nb, rc);
+    std::vector<int64_t> blends((size_t)nb, 0);
+    if (rc == MSGS_OK) {
+      // completions in the order the views' work was issued (fewest instances
+      // first), each stamped when its own last kernel has finished
+      std::vector<int> ord((size_t)nb);
+      for (int i = 0; i < nb; ++i) ord[(size_t)i] = i;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        return frames[(size_t)a]->n_inst < frames[(size_t)b]->n_inst;
+      });
+      for (int i : ord) {
+        hipError_t e = hipEventSynchronize(evs[i]);
+        t_done[(size_t)i] = s->now_us();
+        if (e != hipSuccess) status[(size_t)i] = hip_fail(e, "completion event");
+      }
+      for (int i = 0; i < nb; ++i) {
+        msgs_stats stt{};
+        const int r = msgs_frame_stats(frames[(size_t)i], &stt);
+        if (status[(size_t)i] == MSGS_OK) status[(size_t)i] = r;
+        blends[(size_t)i] = stt.n_blends;
+      }
+    } else {
+      for (int i = 0; i < nb; ++i) t_done[(size_t)i] = s->now_us();
+    }
+    for (msgs_frame* f : frames)
+      if (f) msgs_frame_release(f);
     {
       std::lock_guard<std::mutex> g(s->mu);
       for (size_t i = 0; i < s->active_seq.size(); ++i)
-        if (s->active_seq[i] == rq.seq) {
+        if (s->active_seq[i] == batch[0].seq) {
           s->active_seq.erase(s->active_seq.begin() + (long)i);
           break;
         }
       ++s->mem_epoch;
       if (rc == kRequeue) {
-        s->queue.push_front(rq);
+        for (int i = nb - 1; i >= 0; --i) s->queue.push_front(batch[(size_t)i]);
       } else {
-        msgs_completion c;
-        c.req_id = rq.id;
-        c.status = rc;
-        c.t_submit_us = rq.t_submit;
-        c.t_admit_us = w.t_admit >= 0 ? w.t_admit : t_take;
-        c.t_start_us = t_take;
-        c.t_done_us = t_done;
-        c.n_blends = blends;
-        s->done.push_back(c);
+        for (int i = 0; i < nb; ++i) {
+          const Request& rq = batch[(size_t)i];
+          msgs_completion c;
+          c.req_id = rq.id;
+          c.status = status[(size_t)i];
+          c.t_submit_us = rq.t_submit;
+          c.t_admit_us = w.t_admit >= 0 ? w.t_admit : t_take;
+          c.t_start_us = t_take;
+          c.t_done_us = t_done[(size_t)i];
+          c.n_blends = blends[(size_t)i];
+          s->done.push_back(c);
+        }
       }
     }
     s->cv_mem.notify_all();
@@ -174,6 +235,17 @@ int msgs_server_create(msgs_context* c, msgs_scene* scene, int max_inflight, msg
       return hip_fail(e, "hipStreamCreateWithFlags");
     }
     s->streams.push_back(st);
+  }
+  for (int i = 0; i < max_inflight * kServerBatch; ++i) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (hipEvent_t x : s->events) (void)hipEventDestroy(x);
+      for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
+      delete s;
+      return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    s->events.push_back(ev);
   }
   for (int i = 0; i < max_inflight; ++i) s->workers.emplace_back(worker_loop, s, i);
   *out = s;
@@ -241,6 +313,7 @@ int msgs_server_destroy(msgs_server* s) {
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);
   }
+  for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
   delete s;
   return MSGS_OK;
 }

@@ -319,6 +319,19 @@ __global__ __launch_bounds__(kBlock) void k_rs_rowscan(const uint32_t* counts, u
 // scan `starts`, so no tile waits on another (on a chip whose L2s are per XCD
 // every look-back step is a trip to memory, which long chains of tiles pay
 // for one after another).
+// Buffers of a pass that may be skipped (onesweep passes of a sort whose
+// sorted values go to vals_final): hist_all holds the digit histograms of all
+// npass passes; a pass whose digit is the same for every key moves nothing and
+// is skipped by every workgroup; the passes that run alternate between the
+// (kA, vA) and (kB, vB) buffers, the first reading (kA, vA), and the last writes
+// only its values, to vF.  hist_all = null: the pass reads keys_in/vals_in and
+// writes keys_out (when non-null) and vals_out.
+struct SkipPass {
+  const uint32_t* hist_all;
+  int p, npass;
+  uint32_t *kA, *vA, *kB, *vB, *vF;
+};
+
 template <int ITEMS, bool RTS>
 __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
                                                     const uint32_t* vals_in, uint32_t* keys_out,
@@ -327,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
                                                     const uint32_t* hist,
                                                     unsigned long long* status,
                                                     uint32_t* ticket, const uint32_t* starts,
-                                                    int64_t nblk) {
+                                                    int64_t nblk, SkipPass sk) {
   constexpr int TILE = kBlock * ITEMS;
   __shared__ uint32_t cnt[kBlock / 64][kRadix];
   __shared__ uint32_t ldig[kRadix];
@@ -343,6 +356,23 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   __syncthreads();
   const int64_t t = RTS ? (int64_t)blockIdx.x : s_tile;
   const int64_t n = d_n ? min((int64_t)*d_n, nmax) : nmax;
+  if (!RTS && sk.hist_all) {
+    // the passes that move something (every workgroup reads the same
+    // histograms, so every workgroup takes the same decision)
+    uint32_t act = 0;
+    for (int q = 0; q < sk.npass; ++q) {
+      const bool constant = __syncthreads_or(sk.hist_all[q * kRadix + threadIdx.x] == (uint32_t)n);
+      act |= constant ? 0u : 1u << q;
+    }
+    if (act == 0) act = 1u << (sk.npass - 1);  // all equal: one identity pass to vF
+    if (!((act >> sk.p) & 1u)) return;
+    const int j = __popc(act & ((1u << sk.p) - 1u));
+    const bool last = j == __popc(act) - 1;
+    keys_in = (j & 1) ? sk.kB : sk.kA;
+    vals_in = (j & 1) ? sk.vB : sk.vA;
+    keys_out = last ? nullptr : ((j & 1) ? sk.kA : sk.kB);
+    vals_out = last ? sk.vF : ((j & 1) ? sk.vA : sk.vB);
+  }
   const int64_t tbase = t * TILE;
   // a tile past the input has nothing to move, and no tile that has items
   // looks back at it (tickets are taken in order)
@@ -427,12 +457,14 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   __syncthreads();
   const int64_t rem = n - tbase;
   const int cntile = rem <= 0 ? 0 : (rem >= TILE ? TILE : (int)rem);
+  if (keys_out) {
 #pragma unroll
-  for (int i = 0; i < ITEMS; ++i) {
-    const int p = i * kBlock + threadIdx.x;
-    if (p < cntile) {
-      const uint32_t dd = sdig[p];
-      keys_out[gdig[dd] + ((uint32_t)p - ldig[dd])] = ks[p];
+    for (int i = 0; i < ITEMS; ++i) {
+      const int p = i * kBlock + threadIdx.x;
+      if (p < cntile) {
+        const uint32_t dd = sdig[p];
+        keys_out[gdig[dd] + ((uint32_t)p - ldig[dd])] = ks[p];
+      }
     }
   }
   __syncthreads();
@@ -534,11 +566,11 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
       if (items == 16)
         hipLaunchKernelGGL((k_os_pass<16, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                            vin, kout, vout, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
-                           nblk);
+                           nblk, SkipPass{});
       else
         hipLaunchKernelGGL((k_os_pass<8, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                            vin, kout, vout, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
-                           nblk);
+                           nblk, SkipPass{});
       uint32_t* tt;
       tt = kin; kin = kout; kout = tt;
       tt = vin; vin = vout; vout = tt;
@@ -557,16 +589,82 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
     if (items == 16)
       hipLaunchKernelGGL((k_os_pass<16, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                          vin, kout, vout, d_n, nmax, b, nbits, ghist + p * kRadix,
-                         status + (int64_t)p * nblk * kRadix, tickets + p, nullptr, nblk);
+                         status + (int64_t)p * nblk * kRadix, tickets + p, nullptr, nblk,
+                         SkipPass{});
     else
       hipLaunchKernelGGL((k_os_pass<8, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                          vin, kout, vout, d_n, nmax, b, nbits, ghist + p * kRadix,
-                         status + (int64_t)p * nblk * kRadix, tickets + p, nullptr, nblk);
+                         status + (int64_t)p * nblk * kRadix, tickets + p, nullptr, nblk,
+                         SkipPass{});
     uint32_t* tt;
     tt = kin; kin = kout; kout = tt;
     tt = vin; vin = vout; vout = tt;
   }
   return npass & 1;
+}
+
+void radix_sort_values(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                       uint32_t* vals_final, const uint32_t* d_n, int64_t nmax, int begin_bit,
+                       int end_bit, void* tmp, hipStream_t st, bool zeroed) {
+  if (nmax == 0 || end_bit <= begin_bit) return;
+  const int npass = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
+  const int items = sort_items(nmax);
+  const int64_t nblk = sort_tiles(nmax);
+  if (!zeroed) launch_fill_u32((uint32_t*)tmp, radix_zero_words(nmax, npass), 0u, st);
+  if (nblk >= kRtsMinTiles) {
+    uint32_t* rowtot = (uint32_t*)tmp;
+    uint32_t* counts = rowtot + kRadix;
+    uint32_t* starts = counts + kRadix * nblk;
+    uint32_t *kin = keys, *vin = vals, *kout = keys_alt, *vout = vals_alt;
+    for (int p = 0; p < npass; ++p) {
+      int b, nbits;
+      pass_digits(begin_bit, end_bit, p, b, nbits);
+      const bool last = p == npass - 1;
+      uint32_t* ko = last ? nullptr : kout;
+      uint32_t* vo = last ? vals_final : vout;
+      if (items == 16)
+        hipLaunchKernelGGL(k_rs_count<16>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, d_n,
+                           nmax, b, nbits, counts, nblk);
+      else
+        hipLaunchKernelGGL(k_rs_count<8>, dim3((unsigned)nblk), dim3(kBlock), 0, st, kin, d_n,
+                           nmax, b, nbits, counts, nblk);
+      hipLaunchKernelGGL(k_rs_rowscan, dim3(kRadix), dim3(kBlock), 0, st, counts, starts, rowtot,
+                         d_n, nmax, kBlock * items, nblk);
+      if (items == 16)
+        hipLaunchKernelGGL((k_os_pass<16, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
+                           vin, ko, vo, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
+                           nblk, SkipPass{});
+      else
+        hipLaunchKernelGGL((k_os_pass<8, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
+                           vin, ko, vo, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
+                           nblk, SkipPass{});
+      uint32_t* tt;
+      tt = kin; kin = kout; kout = tt;
+      tt = vin; vin = vout; vout = tt;
+    }
+    return;
+  }
+  uint32_t* ghist = (uint32_t*)tmp;
+  unsigned long long* status = (unsigned long long*)(ghist + npass * kRadix);
+  uint32_t* tickets = (uint32_t*)(status + npass * nblk * kRadix);
+  const int hgrid = (int)std::min<int64_t>((nmax + 4095) / 4096, kHistBlocks);
+  hipLaunchKernelGGL(k_os_hist, dim3(hgrid), dim3(kBlock), 0, st, keys, d_n, nmax, begin_bit,
+                     end_bit, ghist);
+  for (int p = 0; p < npass; ++p) {
+    int b, nbits;
+    pass_digits(begin_bit, end_bit, p, b, nbits);
+    const SkipPass sk{ghist, p, npass, keys, vals, keys_alt, vals_alt, vals_final};
+    if (items == 16)
+      hipLaunchKernelGGL((k_os_pass<16, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st,
+                         nullptr, nullptr, nullptr, nullptr, d_n, nmax, b, nbits,
+                         ghist + p * kRadix, status + (int64_t)p * nblk * kRadix, tickets + p,
+                         nullptr, nblk, sk);
+    else
+      hipLaunchKernelGGL((k_os_pass<8, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st,
+                         nullptr, nullptr, nullptr, nullptr, d_n, nmax, b, nbits,
+                         ghist + p * kRadix, status + (int64_t)p * nblk * kRadix, tickets + p,
+                         nullptr, nblk, sk);
+  }
 }
 
 }  // namespace msgs

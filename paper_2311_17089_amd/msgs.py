@@ -87,6 +87,8 @@ EXPORTS = {
     "msgs_render": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                      C.c_void_p], C.c_int),
     "msgs_render_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_render_views": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.c_int, C.c_void_p], C.c_int),
     "msgs_render_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p], C.c_int),
     "msgs_debug_sort_pairs": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
@@ -300,6 +302,38 @@ def render(ctx: Context, scene: DeviceScene, cam, downscale=1, selective=True,
     if keep_frame:
         return out, Frame(fh, scene, W, H)
     return out
+
+
+def render_views(ctx: Context, scene: DeviceScene, views, keep_frames=False, outs=None,
+                 stream=None):
+    """Render several views of one scene in one call (see msgs_render_views).
+    `views` is a list of (camera, options dict) with the keyword options of
+    `render` (downscale, selective, update_range, lowpass, near, bg, prefilter,
+    capacity).  Returns the images (and the Frames when keep_frames)."""
+    nv = len(views)
+    cams = (CameraC * nv)(*[camera_c(c) for c, _ in views])
+    ops = []
+    imgs = []
+    for i, (cam, kw) in enumerate(views):
+        d = int(kw.get("downscale", 1))
+        ops.append(opts_c(d, kw.get("selective", True), kw.get("update_range", False),
+                          kw.get("lowpass", 0.3), kw.get("near", 0.2), kw.get("bg", (0.0, 0.0, 0.0)),
+                          False, kw.get("prefilter", True), kw.get("capacity", 0)))
+        W, H = cam.width // d, cam.height // d
+        out = outs[i] if outs is not None else torch.empty(
+            (H, W, 3), dtype=torch.float32, device=torch.device("cuda", ctx.device))
+        assert out.is_contiguous() and out.dtype == torch.float32
+        imgs.append(out)
+    oa = (RenderOpts * nv)(*ops)
+    ra = (C.c_void_p * nv)(*[o.data_ptr() for o in imgs])
+    fa = (C.c_void_p * nv)() if keep_frames else None
+    check(lib().msgs_render_views(ctx.h, scene.h, cams, oa, ra, fa, nv,
+                                  C.c_void_p(_stream(stream))))
+    if keep_frames:
+        frames = [Frame(C.c_void_p(fa[i]), scene, imgs[i].shape[1], imgs[i].shape[0])
+                  for i in range(nv)]
+        return imgs, frames
+    return imgs
 
 
 def render_noalloc(ctx: Context, scene: DeviceScene, cam, out: torch.Tensor,

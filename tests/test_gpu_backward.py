@@ -51,18 +51,29 @@ def _gpu_grads(ctx, sc, cam, ds, Gw, selective=True, bg=(0, 0, 0)):
     return out
 
 
-@pytest.mark.parametrize("seed,W,H,ds,selective,bg", [
-    (201, 64, 48, 1, True, (0, 0, 0)),
-    (202, 100, 70, 1, False, (0.2, 0.4, 0.6)),
-    (203, 160, 120, 2, True, (0, 0, 0)),
+@pytest.mark.parametrize("seed,W,H,ds,selective,bg,counts", [
+    (201, 64, 48, 1, True, (0, 0, 0), (600, 150, 40)),
+    (202, 100, 70, 1, False, (0.2, 0.4, 0.6), (600, 150, 40)),
+    (203, 160, 120, 2, True, (0, 0, 0), (600, 150, 40)),
+    # dense: 600-2100 instances per tile, so the replay splits every tile list
+    # into several 256-position blocks that start from the forward's stored
+    # boundary state.  dL/dRGB is positive here: with random signs a Gaussian's
+    # colour gradient over its ~300 pixels cancels by up to 1e4, and fp32 then
+    # carries ~1e-3 relative error in that sum whatever the replay order
+    # (measured on case 204: 1.16x the bar with the block replay, 1.25x with
+    # the whole-tile replay it replaced)
+    (204, 48, 40, 1, False, (0.3, 0.1, 0.2), (4000, 1000, 250)),
+    (206, 64, 48, 1, True, (0, 0, 0), (8000, 2000, 500)),
 ])
-def test_gradient_matches_oracle(ctx, seed, W, H, ds, selective, bg):
+def test_gradient_matches_oracle(ctx, seed, W, H, ds, selective, bg, counts):
     _say(f"  backward seed={seed} {W}x{H} ds={ds}")
-    sc = G.make_scene([600, 150, 40], seed, 3, [-3.4, -2.4, -1.6], sh_std=0.25)
+    sc = G.make_scene(list(counts), seed, 3, [-3.4, -2.4, -1.6], sh_std=0.25)
     sc = O.calibrate(sc, G.calibration_cameras(seed + 1000, W, H, 1.1 * W))
     cam = G.lookat_camera(G.sphere_poses(1, seed, 2.6, 3.2)[0], W, H, 1.1 * W)
     F = grad64.Frozen(sc, cam, ds, selective=selective, bg=bg)
     Gw = np.random.default_rng(seed).standard_normal((F.pix.shape[0], 3))
+    if sum(counts) > 1000:
+        Gw = np.abs(Gw) + 0.1
     ref = F.grad(Gw)
     got = _gpu_grads(ctx, sc, cam, ds, Gw, selective, bg)
     for k in GROUPS:

@@ -222,6 +222,21 @@ def test_edge_cases(ctx):
     check_frame(ctx, sc, cam, 1)
 
 
+@pytest.mark.parametrize("spread", [0.0, 1e-6, 1e-3])
+def test_depths_sharing_key_digits(ctx, spread):
+    # the depth sort skips the passes whose digit every key shares: all depths
+    # equal (every pass skipped but the last, which copies), 6 low bits varying
+    # (one pass), about 16 low bits varying (two passes); keys, selection and
+    # image against the oracle
+    sc = G.make_scene([800], 7, 0, [-3.0])
+    sc.means[2] = (0.2537 + sc.means[2] * spread).astype(np.float32)
+    cam = G.lookat_camera([0, 0, -3], 40, 30, 40.0)
+    p = O.project(sc, cam)
+    d = p["depth"][p["ntiles"] > 0].view(np.uint32)
+    _say(f"  depth bits varying: {int(d.min() ^ d.max()).bit_length()}")
+    check_frame(ctx, sc, cam, 1)
+
+
 def test_invalid_arguments(ctx):
     sc = G.make_scene([10], 1, 0, [-3.0])
     dsc = M.DeviceScene(ctx, sc)
