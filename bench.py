@@ -192,13 +192,7 @@ def serving_replay(M, G, n_req=512, rate_hz=200.0, inflight=4, selective=True):
     minus submission time, plus how late the submission was)."""
     import numpy as np
     import torch
-    if not hasattr(serving_replay, "scene"):
-        ctx = M.Context(0)
-        sc = G.large_scene(3_000_000, 4, 3)
-        dsc = M.DeviceScene(ctx, sc)
-        M.calibrate(ctx, dsc, G.calibration_cameras(1003, 1920, 1080, 2250.0))
-        serving_replay.scene = (ctx, dsc)
-    ctx, dsc = serving_replay.scene
+    ctx, dsc = c3_scene(M, G)
     stream = G.request_stream(seed=4, n=n_req, rate_hz=rate_hz)
     outs = [torch.empty((cam.height // d, cam.width // d, 3), device="cuda") for _, cam, d in stream]
     torch.cuda.synchronize()
@@ -234,11 +228,102 @@ def serving_replay(M, G, n_req=512, rate_hz=200.0, inflight=4, selective=True):
             "p50_ms_by_downscale": {str(k): float(np.percentile(v, 50)) for k, v in sorted(per_ds.items())}}
 
 
+def c3_scene(M, G):
+    """The resident 3M-Gaussian, 4-level scene (SH degree 3) with its
+    selection ranges calibrated on the GPU at 1920x1080, shared by the
+    serving replay and the differentiation configuration."""
+    if not hasattr(c3_scene, "scene"):
+        ctx = M.Context(0)
+        sc = G.large_scene(3_000_000, 4, 3)
+        dsc = M.DeviceScene(ctx, sc)
+        M.calibrate(ctx, dsc, G.calibration_cameras(1003, 1920, 1080, 2250.0))
+        c3_scene.scene = (ctx, dsc)
+    return c3_scene.scene
+
+
+def frame_timing(M, ctx, dsc, cam, ds, backward, reps=20):
+    """One frame (forward, or forward + backward of a seeded upstream
+    gradient): its counts, the sum of its stage spans in profiled eager runs
+    (the library's HIP events around each stage, which add their own
+    overhead), and the wall time per frame of a captured HIP graph of it
+    (fixed tile-list capacity 1.25x the counted instances + 4096) replayed
+    `reps` times back to back (the headline figures)."""
+    import torch
+    W, H = cam.width // ds, cam.height // ds
+    g = torch.Generator().manual_seed(700 + ds)
+    dl = torch.randn((H, W, 3), generator=g).cuda() * 1e-3 if backward else None
+
+    def once(prof=False, capacity=0):
+        _, fr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, profile=prof,
+                         capacity=capacity)
+        if backward:
+            M.render_backward(ctx, fr, dl)
+        return fr
+
+    fr = once()
+    st = fr.stats()
+    fr.release()
+    cap = int(st["n_instances"] * 1.25) + 4096
+    dev_us = 0.0
+    for _ in range(3):
+        fr = once(prof=True)
+        dev_us += sum(fr.stats()["stage_us"])
+        fr.release()
+    once(capacity=cap).release()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr, stream=side):
+        _, gfr = M.render(ctx, dsc, cam, downscale=ds, keep_frame=True, stream=side, capacity=cap)
+        if backward:
+            M.render_backward(ctx, gfr, dl, stream=side)
+    for _ in range(3):
+        gr.replay()
+    torch.cuda.synchronize()
+    assert gfr.stats()["n_blends"] == st["n_blends"]
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        gr.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    del gr
+    torch.cuda.synchronize()
+    gfr.release()
+    return {"width": W, "height": H, "n_selected": st["n_selected"],
+            "n_instances": st["n_instances"], "blends": st["n_blends"],
+            "ms_per_frame": ms, "frames_per_s": 1e3 / ms,
+            "blends_per_s": st["n_blends"] / (ms / 1e3),
+            "stage_us_sum_profiled": dev_us / 3, "reps": reps}
+
+
+def other_configs(M, G):
+    """The two other workloads of the method's benchmark set, timed frame by
+    frame: the single-level 10k-Gaussian scene at 128x128 (forward only) and
+    the 3M-Gaussian, 4-level scene at 1920x1080, 1x and 8x (forward plus the
+    adjoint backward)."""
+    import numpy as np
+    ctx = M.Context(0)
+    sc1 = G.single_level_scene()
+    d1 = M.DeviceScene(ctx, sc1)
+    cam1 = G.Camera(R=np.eye(3, dtype=np.float32).reshape(9), t=np.array([0, 0, 3], np.float32),
+                    fx=150.0, fy=150.0, cx=64.0, cy=64.0, width=128, height=128)
+    out = {"single_level_10k_128px": dict(frame_timing(M, ctx, d1, cam1, 1, False, reps=200),
+                                          n_gaussians=sc1.n, passes="forward")}
+    d1.close()
+    ctx3, d3 = c3_scene(M, G)
+    cam3 = G.Camera(R=np.eye(3, dtype=np.float32).reshape(9), t=np.array([0, 0, 3], np.float32),
+                    fx=2250.0, fy=2250.0, cx=960.0, cy=540.0, width=1920, height=1080)
+    out["four_level_3m_1080p"] = {
+        str(ds): dict(frame_timing(M, ctx3, d3, cam3, ds, True), passes="forward + backward")
+        for ds in (1, 8)}
+    return out
+
+
 def aggregation_bench(M, G, reps=3):
     """Alg. 1 on the GPU: the level-0 Gaussians of the 3M-Gaussian scene
     (2,258,824 of them, SH degree 3) and 8 training cameras at radius 3,
     1920x1080; level 1 (downscale 4, 200^3 voxels) and then level 2 (16,
-    133^3) built on top of it, as msgs.build_levels does.  Timed per level:
+    133^3) built on top of it, as msgs_build_levels does.  Timed per level:
     one aggregate_level call on the resident scene (minimal coverage over the
     cameras, voxel keys, sort, segmented average pooling, enlargement), device
     synchronised on both sides."""
@@ -253,17 +338,16 @@ def aggregation_bench(M, G, reps=3):
                                s_min=sc.s_min[keep].copy())
     cams = G.calibration_cameras(1003, 1920, 1080, 2250.0)
     ctx = M.Context(0)
-    extent = M.camera_extent(cams)
     res = {}
     scene = base
     for level in (1, 2):
         dsc = M.DeviceScene(ctx, scene)
-        part = M.aggregate_level(ctx, dsc, cams, level, 2.0, extent)  # warm-up
+        part = M.aggregate_level(ctx, dsc, cams, level)  # warm-up (library defaults)
         torch.cuda.synchronize()
         ts = []
         for _ in range(reps):
             t0 = time.perf_counter()
-            part = M.aggregate_level(ctx, dsc, cams, level, 2.0, extent)
+            part = M.aggregate_level(ctx, dsc, cams, level)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         below = int(scene.n)
@@ -474,6 +558,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-training", action="store_true")
     ap.add_argument("--no-aggregation", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=30)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one serial step and a 1 GiB elementwise copy, for HBM counter runs")
@@ -767,6 +852,10 @@ def main():
         out["serving"] = {"selective": serving_replay(M, G, selective=True),
                           "single_scale": serving_replay(M, G, selective=False),
                           "saturation": serving_sweep(M, G)}
+    if not args.no_other_configs:
+        print("bench: 10k-Gaussian 128x128 and 3M-Gaussian 1080p frames", file=sys.stderr,
+              flush=True)
+        out["other_configs"] = other_configs(M, G)
     if not args.no_training:
         print("bench: training step (6M Gaussians, 8 views)", file=sys.stderr, flush=True)
         out["training_step"] = training_step(M, G)

@@ -296,25 +296,56 @@ typedef struct {
 } msgs_gaussians;
 
 /* Coarse-level aggregation (Alg. 1 for one target level; supplementary
- * "Details of Gaussian Aggregation"):
+ * section on the details of Gaussian aggregation):
  *   every Gaussian of a level below `level` is projected with every camera of
  *   `cams` at downscale 4^level; its pixel coverage counts for a camera that
  *   draws it (in front, non-empty level set, at least one tile); Gaussians whose
- *   smallest such coverage is below s_thresh (S_T, 2 px) are binned by their
+ *   smallest such coverage is below s_thresh (S_T) are binned by their
  *   normalised position (x / extent inside the cube of half side `extent`,
  *   (2 - extent / m) x / m outside, m the max-norm) on a grid of `grid` voxels
- *   per axis over [-2, 2]^3 (the paper uses grid = floor(400 / (level + 1)));
- *   each occupied voxel yields one Gaussian: the mean position, unit rotation,
- *   linear scale, opacity and SH of its members, the scale multiplied by
- *   s_thresh / (mean coverage of the members).
+ *   per axis over [-2, 2]^3; each occupied voxel yields one Gaussian: the mean
+ *   position, unit rotation, linear scale, opacity and SH of its members, the
+ *   scale multiplied by s_thresh / (mean coverage of the members).
+ * Defaults (pass 0): s_thresh = 2 px (S_T of Sec. 4.1); extent = the half side
+ * of the origin-centred cube holding every camera centre (the extent of the
+ * training cameras); grid = floor(400 / (level + 1)) (the paper's (400/l_m)^3
+ * grid with 1-based l_m).
  * The new Gaussians are written in ascending voxel order to `out`; *n_out
  * receives their number.  Synchronous.  Errors: MSGS_E_INVALID (level outside
- * [1, n_levels - 1], grid outside [1, 255], non-positive extent or threshold,
- * no camera), MSGS_E_CAPACITY (more than out->cap Gaussians: *n_out holds the
- * number needed and nothing is written). */
+ * [1, n_levels - 1], grid outside [1, 255], negative or NaN threshold, extent
+ * or grid, no camera), MSGS_E_CAPACITY (more than out->cap Gaussians: *n_out
+ * holds the number needed and nothing is written). */
 int msgs_aggregate_level(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cams,
                          int ncams, int level, float s_thresh, float extent, int grid,
                          const msgs_gaussians* out, int64_t* n_out, void* stream);
+
+/* A whole scene as caller-owned device planes of pitch `cap` (room for cap
+ * Gaussians): the scene_desc arrays, writable. */
+typedef struct {
+  float* means;    /* [3][cap] */
+  float* scales;   /* [3][cap] */
+  float* quats;    /* [4][cap] */
+  float* opacity;  /* [cap] */
+  float* sh;       /* [3 (D+1)^2][cap] */
+  uint8_t* level;  /* [cap] */
+  float* s_max;    /* [cap] */
+  float* s_min;    /* [cap] */
+  int64_t cap;
+} msgs_scene_out;
+
+/* Alg. 1 over every coarse level: the base Gaussians (normally all of level
+ * 0; host or device arrays, base->ptrs_on_device) are copied to `out`, then for
+ * l = 1 .. n_levels - 1 the Gaussians of the levels below l built so far are
+ * aggregated as msgs_aggregate_level does (threshold s_thresh, 0 = 2 px; the
+ * cameras' extent; floor(400 / (l + 1)) voxels per axis) and appended as level
+ * l with the uncalibrated range (s_max 0, s_min +inf).  *n_out receives the
+ * scene's size, added[l - 1] the Gaussians level l received (n_levels - 1
+ * entries).  Synchronous.  MSGS_E_CAPACITY when `out` cannot hold the scene:
+ * *n_out then holds the size needed up to the level that did not fit (a larger
+ * out may need more for later levels). */
+int msgs_build_levels(msgs_context* ctx, const msgs_scene_desc* base, const msgs_camera* cams,
+                      int ncams, int n_levels, float s_thresh, const msgs_scene_out* out,
+                      int64_t* n_out, int64_t* added, void* stream);
 
 /* Release a frame (its device memory is returned on the frame's stream). */
 int msgs_frame_release(msgs_frame* f);

@@ -633,6 +633,16 @@ void launch_gather_counts(const CounterList& cl, unsigned long long* out, hipStr
   if (cl.n > 0) hipLaunchKernelGGL(k_gather_counts, dim3(1), dim3(64), 0, st, cl, out);
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(kBlock), 0, st, p, n, v);
+}
+
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kBlock), 0, st, p, n, v);

@@ -473,25 +473,35 @@ int msgs_scene_get_ranges(const msgs_scene* s, float* smax, float* smin) {
   return MSGS_OK;
 }
 
-int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams, int ncams,
-                         int level, float s_thresh, float extent, int grid,
-                         const msgs_gaussians* out, int64_t* n_out, void* stream) {
-  if (!c || !s || !cams || !out || !n_out) return fail(MSGS_E_INVALID, "null argument");
-  if (s->ctx != c) return fail(MSGS_E_INVALID, "scene belongs to another context");
-  if (ncams < 1) return fail(MSGS_E_INVALID, "at least one camera is needed");
-  if (level < 1 || level >= s->view.n_levels)
-    return fail(MSGS_E_INVALID, "target level must be in [1, n_levels - 1]");
-  if (level > 12) return fail(MSGS_E_INVALID, "target level too large");
-  if (grid < 1 || grid > 255) return fail(MSGS_E_INVALID, "grid must be in [1, 255]");
-  if (!(extent > 0.0f) || !(s_thresh > 0.0f))
-    return fail(MSGS_E_INVALID, "extent and threshold must be positive");
-  if (out->cap < 0 || (out->cap > 0 && (!out->means || !out->scales || !out->quats ||
-                                        !out->opacity || !out->sh)))
-    return fail(MSGS_E_INVALID, "null output array");
-  hipError_t e = hipSetDevice(c->device);
-  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t n = s->view.n;
+}  // extern "C"
+
+namespace msgs {
+
+// B: half side of the origin-centred axis-aligned cube holding every camera
+// centre -R^T t (fp64, rounded to fp32), the extent of the training cameras
+// that bounds the centre region of the supplementary's normalisation.
+float default_extent(const msgs_camera* cams, int ncams) {
+  double b = 0.0;
+  for (int i = 0; i < ncams; ++i)
+    for (int a = 0; a < 3; ++a) {
+      const double c = -((double)cams[i].R[0 * 3 + a] * cams[i].t[0] +
+                         (double)cams[i].R[1 * 3 + a] * cams[i].t[1] +
+                         (double)cams[i].R[2 * 3 + a] * cams[i].t[2]);
+      b = std::max(b, std::fabs(c));
+    }
+  return (float)b;
+}
+
+// The paper's voxel grid for target level l (0-based): floor(400 / l_m) with
+// the 1-based l_m = l + 1.
+int default_grid(int level) { return 400 / (level + 1); }
+
+// Alg. 1 for one target level over the Gaussians of `view`; the new Gaussians
+// go to out (planes of pitch `stride`, room for out.cap).  Synchronous.
+int aggregate_internal(msgs_context* c, const SceneView& view, const msgs_camera* cams, int ncams,
+                       int level, float s_thresh, float extent, int grid,
+                       const msgs_gaussians& out, int64_t stride, int64_t* n_out, hipStream_t st) {
+  const int64_t n = view.n;
   *n_out = 0;
   if (n == 0) return MSGS_OK;
   std::vector<ViewParams> hv((size_t)ncams);
@@ -500,7 +510,7 @@ int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams
   o.downscale = 1 << (2 * level);
   o.selective = 0;
   for (int i = 0; i < ncams; ++i) {
-    int rc = make_view(&cams[i], &o, s->view.n_levels, &hv[(size_t)i]);
+    int rc = make_view(&cams[i], &o, view.n_levels, &hv[(size_t)i]);
     if (rc != MSGS_OK) return rc;
   }
   ViewParams* dv = nullptr;
@@ -509,6 +519,8 @@ int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams
   float* smin = nullptr;
   unsigned long long* ctr = nullptr;
   void *stmp = nullptr, *ctmp = nullptr;
+  uint32_t* pos = nullptr;
+  float* rows = nullptr;
   Carve tmp;
   tmp.add((void**)&dv, sizeof(ViewParams) * (size_t)ncams);
   tmp.add((void**)&keys, (size_t)n * 4);
@@ -519,18 +531,17 @@ int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams
   tmp.add((void**)&segidx, (size_t)n * 4);
   tmp.add((void**)&starts, (size_t)(n + 1) * 4);
   tmp.add((void**)&smin, (size_t)n * 4);
-  uint32_t* pos = nullptr;
-  float* rows = nullptr;
   tmp.add((void**)&pos, (size_t)n * 4);
-  tmp.add((void**)&rows, (size_t)n * 4 * agg_row_floats(s->view.sh_degree));
+  tmp.add((void**)&rows, (size_t)n * 4 * agg_row_floats(view.sh_degree));
   tmp.add((void**)&ctr, 16);
   tmp.add(&ctmp, scan_tmp_bytes(n));
   tmp.add(&stmp, radix_tmp_bytes(n, radix_passes(0, 24)));
   int rc = tmp.alloc(c, st);
   if (rc != MSGS_OK) return rc;
-  e = hipMemcpyAsync(dv, hv.data(), sizeof(ViewParams) * (size_t)ncams, hipMemcpyHostToDevice, st);
+  hipError_t e =
+      hipMemcpyAsync(dv, hv.data(), sizeof(ViewParams) * (size_t)ncams, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) {
-    launch_agg_cover(s->view, dv, ncams, level, s_thresh, extent, grid, keys, vals, smin, st);
+    launch_agg_cover(view, dv, ncams, level, s_thresh, extent, grid, keys, vals, smin, st);
     // stable sort by voxel (the 24-bit key): ends in the second buffers after 3 passes
     const int odd = radix_sort_pairs(keys, vals, keys2, vals2, nullptr, n, 0, 24, stmp, st);
     const uint32_t* sk = odd ? keys2 : keys;
@@ -543,13 +554,12 @@ int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess) {
       *n_out = (int64_t)nseg;
-      if ((int64_t)nseg > out->cap) {
+      if ((int64_t)nseg > out.cap) {
         rc = fail(MSGS_E_CAPACITY, "aggregation output needs " + std::to_string(nseg) +
-                                       " Gaussians, capacity " + std::to_string(out->cap));
+                                       " Gaussians, capacity " + std::to_string(out.cap));
       } else {
-        launch_agg_reduce(s->view, sk, sv, starts, (int64_t)nseg, smin, s_thresh, pos, rows,
-                          out->means, out->scales, out->quats, out->opacity, out->sh, out->cap,
-                          st);
+        launch_agg_reduce(view, sk, sv, starts, (int64_t)nseg, smin, s_thresh, pos, rows,
+                          out.means, out.scales, out.quats, out.opacity, out.sh, stride, st);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(st);
       }
@@ -557,6 +567,164 @@ int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams
   }
   if (e != hipSuccess) rc = hip_fail(e, "aggregation");
   c->cache.free(c, tmp.base, st);
+  return rc;
+}
+
+// Aggregation arguments: 0 selects the paper's default (S_T = 2 px, the camera
+// extent, floor(400 / (level + 1)) voxels per axis); negative or NaN values are
+// invalid.
+static int agg_defaults(const msgs_camera* cams, int ncams, int level, float* s_thresh,
+                        float* extent, int* grid) {
+  if (!(*s_thresh >= 0.0f) || !(*extent >= 0.0f) || *grid < 0)
+    return fail(MSGS_E_INVALID, "threshold, extent and grid must be >= 0 (0: the default)");
+  if (*s_thresh == 0.0f) *s_thresh = 2.0f;
+  if (*extent == 0.0f) *extent = default_extent(cams, ncams);
+  if (*grid == 0) *grid = default_grid(level);
+  if (*grid < 1 || *grid > 255) return fail(MSGS_E_INVALID, "grid must be in [1, 255]");
+  if (!(*extent > 0.0f) || !std::isfinite(*extent))
+    return fail(MSGS_E_INVALID, "the camera extent must be positive and finite");
+  return MSGS_OK;
+}
+
+}  // namespace msgs
+
+extern "C" {
+
+int msgs_aggregate_level(msgs_context* c, msgs_scene* s, const msgs_camera* cams, int ncams,
+                         int level, float s_thresh, float extent, int grid,
+                         const msgs_gaussians* out, int64_t* n_out, void* stream) {
+  if (!c || !s || !cams || !out || !n_out) return fail(MSGS_E_INVALID, "null argument");
+  if (s->ctx != c) return fail(MSGS_E_INVALID, "scene belongs to another context");
+  if (ncams < 1) return fail(MSGS_E_INVALID, "at least one camera is needed");
+  if (level < 1 || level >= s->view.n_levels)
+    return fail(MSGS_E_INVALID, "target level must be in [1, n_levels - 1]");
+  if (level > 12) return fail(MSGS_E_INVALID, "target level too large");
+  int rc = agg_defaults(cams, ncams, level, &s_thresh, &extent, &grid);
+  if (rc != MSGS_OK) return rc;
+  if (out->cap < 0 || (out->cap > 0 && (!out->means || !out->scales || !out->quats ||
+                                        !out->opacity || !out->sh)))
+    return fail(MSGS_E_INVALID, "null output array");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return aggregate_internal(c, s->view, cams, ncams, level, s_thresh, extent, grid, *out, out->cap,
+                            n_out, (hipStream_t)stream);
+}
+
+int msgs_build_levels(msgs_context* c, const msgs_scene_desc* base, const msgs_camera* cams,
+                      int ncams, int n_levels, float s_thresh, const msgs_scene_out* out,
+                      int64_t* n_out, int64_t* added, void* stream) {
+  if (!c || !base || !cams || !out || !n_out || !added)
+    return fail(MSGS_E_INVALID, "null argument");
+  if (ncams < 1) return fail(MSGS_E_INVALID, "at least one camera is needed");
+  if (n_levels < 1 || n_levels > 8) return fail(MSGS_E_INVALID, "n_levels must be 1..8");
+  if (base->n < 0 || base->n >= ((int64_t)1 << 31)) return fail(MSGS_E_INVALID, "bad base size");
+  if (base->sh_degree < 0 || base->sh_degree > 3)
+    return fail(MSGS_E_INVALID, "sh_degree must be 0..3");
+  const int64_t n0 = base->n, cap = out->cap;
+  const int K3 = 3 * (base->sh_degree + 1) * (base->sh_degree + 1);
+  if (n0 > 0 && (!base->means || !base->scales || !base->quats || !base->opacity || !base->sh ||
+                 !base->level || !base->s_max || !base->s_min))
+    return fail(MSGS_E_INVALID, "null base array");
+  if (cap < n0) {
+    *n_out = n0;
+    return fail(MSGS_E_CAPACITY, "the output must hold at least the base Gaussians");
+  }
+  if (cap > 0 && (!out->means || !out->scales || !out->quats || !out->opacity || !out->sh ||
+                  !out->level || !out->s_max || !out->s_min))
+    return fail(MSGS_E_INVALID, "null output array");
+  float extent = 0.0f;
+  int grid0 = 0;
+  int rc = agg_defaults(cams, ncams, 1, &s_thresh, &extent, &grid0);
+  if (rc != MSGS_OK) return rc;
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  for (int l = 0; l < n_levels - 1; ++l) added[l] = 0;
+  // planar copies between pitches (elements of `esz` bytes, `rows` planes)
+  auto copy_planar = [&](void* dst, int64_t dpitch, const void* src, int64_t spitch, int64_t cnt,
+                         int rows, size_t esz, hipMemcpyKind kind) {
+    if (cnt == 0 || e != hipSuccess) return;
+    e = hipMemcpy2DAsync(dst, (size_t)dpitch * esz, src, (size_t)spitch * esz, (size_t)cnt * esz,
+                         (size_t)rows, kind, st);
+  };
+  const hipMemcpyKind k_in = base->ptrs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  copy_planar(out->means, cap, base->means, n0, n0, 3, 4, k_in);
+  copy_planar(out->scales, cap, base->scales, n0, n0, 3, 4, k_in);
+  copy_planar(out->quats, cap, base->quats, n0, n0, 4, 4, k_in);
+  copy_planar(out->opacity, cap, base->opacity, n0, n0, 1, 4, k_in);
+  copy_planar(out->sh, cap, base->sh, n0, n0, K3, 4, k_in);
+  copy_planar(out->level, cap, base->level, n0, n0, 1, 1, k_in);
+  copy_planar(out->s_max, cap, base->s_max, n0, n0, 1, 4, k_in);
+  copy_planar(out->s_min, cap, base->s_min, n0, n0, 1, 4, k_in);
+  if (e != hipSuccess) return hip_fail(e, "copy of the base Gaussians");
+  int64_t ncur = n0;
+  *n_out = n0;
+  for (int l = 1; l < n_levels && rc == MSGS_OK; ++l) {
+    // the scene built so far as compact planes (the kernels take the count as
+    // the plane pitch)
+    float *m = nullptr, *sc = nullptr, *q = nullptr, *op = nullptr, *sh = nullptr;
+    float *smx = nullptr, *smn = nullptr;
+    uint8_t* lv = nullptr;
+    Carve w;
+    w.add(&m, (size_t)ncur * 12);
+    w.add(&sc, (size_t)ncur * 12);
+    w.add(&q, (size_t)ncur * 16);
+    w.add(&op, (size_t)ncur * 4);
+    w.add(&sh, (size_t)ncur * 4 * K3);
+    w.add(&lv, (size_t)ncur);
+    w.add(&smx, (size_t)ncur * 4);
+    w.add(&smn, (size_t)ncur * 4);
+    rc = w.alloc(c, st);
+    if (rc != MSGS_OK) break;
+    copy_planar(m, ncur, out->means, cap, ncur, 3, 4, hipMemcpyDeviceToDevice);
+    copy_planar(sc, ncur, out->scales, cap, ncur, 3, 4, hipMemcpyDeviceToDevice);
+    copy_planar(q, ncur, out->quats, cap, ncur, 4, 4, hipMemcpyDeviceToDevice);
+    copy_planar(op, ncur, out->opacity, cap, ncur, 1, 4, hipMemcpyDeviceToDevice);
+    copy_planar(sh, ncur, out->sh, cap, ncur, K3, 4, hipMemcpyDeviceToDevice);
+    copy_planar(lv, ncur, out->level, cap, ncur, 1, 1, hipMemcpyDeviceToDevice);
+    copy_planar(smx, ncur, out->s_max, cap, ncur, 1, 4, hipMemcpyDeviceToDevice);
+    copy_planar(smn, ncur, out->s_min, cap, ncur, 1, 4, hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "copy of the scene built so far");
+    } else {
+      SceneView v{};
+      v.n = ncur;
+      v.sh_degree = base->sh_degree;
+      v.n_levels = n_levels;
+      v.means = m;
+      v.scales = sc;
+      v.quats = q;
+      v.opacity = op;
+      v.sh = sh;
+      v.level = lv;
+      v.s_max = smx;
+      v.s_min = smn;
+      msgs_gaussians o{out->means + ncur, out->scales + ncur, out->quats + ncur,
+                       out->opacity + ncur, out->sh + ncur, cap - ncur};
+      int64_t mnew = 0;
+      rc = aggregate_internal(c, v, cams, ncams, l, s_thresh, extent, default_grid(l), o, cap,
+                              &mnew, st);
+      if (rc == MSGS_E_CAPACITY) *n_out = ncur + mnew;
+      if (rc == MSGS_OK && mnew > 0) {
+        // the new level: uncalibrated range (0, +inf)
+        launch_fill_u8(out->level + ncur, mnew, (uint8_t)l, st);
+        launch_fill_u32((uint32_t*)(out->s_max + ncur), mnew, 0u, st);
+        launch_fill_u32((uint32_t*)(out->s_min + ncur), mnew, 0x7f800000u, st);
+        e = hipGetLastError();
+        if (e != hipSuccess) rc = hip_fail(e, "new level fill");
+      }
+      if (rc == MSGS_OK) {
+        added[l - 1] = mnew;
+        ncur += mnew;
+        *n_out = ncur;
+      }
+    }
+    c->cache.free(c, w.base, st);
+  }
+  if (rc == MSGS_OK) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = hip_fail(e, "build levels");
+  }
   return rc;
 }
 

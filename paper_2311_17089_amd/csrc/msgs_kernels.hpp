@@ -43,6 +43,7 @@ void launch_emit(const uint32_t* order, const uint32_t* off, const uint32_t* d_n
                  uint32_t* tvals, uint32_t* emit_base, uint32_t cap, unsigned long long* ctr_fit,
                  hipStream_t st);
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+void launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
 // out[0] = drawable Gaussians, out[1] = tile instances the frame needs,
 // out[2] = instances that fit its capacity (device u64 each), from a frame's
 // counter block
@@ -191,11 +192,12 @@ void launch_agg_starts(const uint32_t* keys, const uint32_t* heads, const uint32
                        int64_t n, uint32_t* starts, hipStream_t st);
 // floats per row of the sorted attribute table (pos: n words, rows: n rows)
 size_t agg_row_floats(int sh_degree);
-// keys/vals: the voxel-sorted (key, index) pairs; starts: nseg + 1 run starts
+// keys/vals: the voxel-sorted (key, index) pairs; starts: nseg + 1 run starts;
+// outputs: planes of pitch `stride`
 void launch_agg_reduce(const SceneView& s, const uint32_t* keys, const uint32_t* vals,
                        const uint32_t* starts, int64_t nseg, const float* smin, float s_thresh,
                        uint32_t* pos, float* rows, float* o_means, float* o_scales,
-                       float* o_quats, float* o_opacity, float* o_sh, int64_t cap,
+                       float* o_quats, float* o_opacity, float* o_sh, int64_t stride,
                        hipStream_t st);
 
 }  // namespace msgs

@@ -27,6 +27,15 @@
 
 namespace msgs {
 
+// Items per thread of sorts below 4M keys, and the predecessors a pass's
+// look-back reads at once.
+#ifndef MSGS_SORT_ITEMS_SMALL
+#define MSGS_SORT_ITEMS_SMALL 8
+#endif
+#ifndef MSGS_PASS_WINDOW
+#define MSGS_PASS_WINDOW 4
+#endif
+
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
@@ -450,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   for (int i = 0; i < ITEMS; ++i) v_[i] = i * 64 + lane < remw ? vin_w[i * 64 + lane] : 0u;
   unsigned long long excl = 0;
   if (!RTS && t > 0 && used) {
-    excl = look_back<4>(status + d, kRadix, t);
+    excl = look_back<MSGS_PASS_WINDOW>(status + d, kRadix, t);
     st_status(st, kFlagP | (excl + bt));
   }
   gdig[d] = gs + (uint32_t)excl;
@@ -482,7 +491,9 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   }
 }
 
-static inline int sort_items(int64_t nmax) { return nmax >= (4ll << 20) ? 16 : 8; }
+static inline int sort_items(int64_t nmax) {
+  return nmax >= (4ll << 20) ? 16 : MSGS_SORT_ITEMS_SMALL;
+}
 
 size_t scan_tmp_bytes(int64_t nmax) {
   const int64_t nb = (nmax + kScanTile - 1) / kScanTile;

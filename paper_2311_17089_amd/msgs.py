@@ -110,6 +110,8 @@ EXPORTS = {
     "msgs_server_destroy": ([C.c_void_p], C.c_int),
     "msgs_aggregate_level": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_float,
                               C.c_float, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "msgs_build_levels": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_float,
+                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
 }
 
 
@@ -530,26 +532,19 @@ class Server:
             self.h = None
 
 
-def camera_extent(cams) -> float:
-    """Half side of the origin-centred axis-aligned cube holding every camera
-    centre (-R^T t), as fp32: the default normalisation extent of aggregation."""
-    b = 0.0
-    for cam in cams:
-        R = np.asarray(cam.R, np.float64).reshape(3, 3)
-        c = -R.T @ np.asarray(cam.t, np.float64)
-        b = max(b, float(np.abs(c).max()))
-    return float(np.float32(b))
+class SceneOut(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p), ("level", C.c_void_p),
+                ("s_max", C.c_void_p), ("s_min", C.c_void_p), ("cap", C.c_int64)]
 
 
-def aggregate_level(ctx: Context, scene: DeviceScene, cams, level: int, s_thresh: float = 2.0,
-                    extent: Optional[float] = None, grid: Optional[int] = None,
-                    stream=None) -> dict:
+def aggregate_level(ctx: Context, scene: DeviceScene, cams, level: int, s_thresh: float = 0.0,
+                    extent: float = 0.0, grid: int = 0, stream=None) -> dict:
     """New Gaussians of `level` aggregated from the small Gaussians below it
-    (see msgs_aggregate_level); returns device tensors in voxel order."""
-    extent = camera_extent(cams) if extent is None else float(extent)
-    grid = 400 // (level + 1) if grid is None else int(grid)
+    (see msgs_aggregate_level; 0 selects the library's default threshold,
+    camera extent and voxel grid); returns device tensors in voxel order."""
     dev = scene.t["means"].device
-    cap = max(1, int((scene.t["level"] < level).sum().item()))
+    cap = max(1, scene.n)
     K3 = 3 * (scene.sh_degree + 1) ** 2
     out = {"means": torch.empty((3, cap), device=dev), "scales": torch.empty((3, cap), device=dev),
            "quats": torch.empty((4, cap), device=dev), "opacity": torch.empty(cap, device=dev),
@@ -558,37 +553,44 @@ def aggregate_level(ctx: Context, scene: DeviceScene, cams, level: int, s_thresh
     arr = (CameraC * len(cams))(*[camera_c(c) for c in cams])
     n_out = C.c_int64()
     check(lib().msgs_aggregate_level(ctx.h, scene.h, arr, len(cams), int(level), float(s_thresh),
-                                     float(extent), grid, C.byref(g), C.byref(n_out),
+                                     float(extent), int(grid), C.byref(g), C.byref(n_out),
                                      C.c_void_p(_stream(stream))))
     m = n_out.value
     return {k: v[..., :m].contiguous() for k, v in out.items()}
 
 
-def build_levels(ctx: Context, scene0, cams, n_levels: int, s_thresh: float = 2.0):
-    """Alg. 1 over every coarse level: starting from the level-0 Gaussians of
-    `scene0` (numpy scenegen.Scene), aggregate for l = 1 .. n_levels - 1 and
-    append each new level (uncalibrated range).  Returns the numpy scene and
-    the number of Gaussians added per level."""
-    import dataclasses
+def build_levels(ctx: Context, scene0, cams, n_levels: int, s_thresh: float = 0.0):
+    """Alg. 1 over every coarse level in the library (msgs_build_levels): from
+    the level-0 Gaussians of `scene0` (numpy scenegen.Scene), aggregate for
+    l = 1 .. n_levels - 1 and append each new level (uncalibrated range).
+    Returns the numpy scene and the number of Gaussians added per level."""
     from .scenegen import Scene
-    scene = dataclasses.replace(scene0, n_levels=n_levels)
-    extent = camera_extent(cams)
-    added = []
-    for l in range(1, n_levels):
-        dsc = DeviceScene(ctx, scene)
-        part = aggregate_level(ctx, dsc, cams, l, s_thresh, extent)
-        torch.cuda.synchronize()
-        dsc.close()
-        m = part["opacity"].numel()
-        added.append(m)
-        host = {k: v.cpu().numpy() for k, v in part.items()}
-        scene = Scene(n=scene.n + m, sh_degree=scene.sh_degree, n_levels=n_levels,
-                      means=np.ascontiguousarray(np.concatenate([scene.means, host["means"]], 1)),
-                      scales=np.ascontiguousarray(np.concatenate([scene.scales, host["scales"]], 1)),
-                      quats=np.ascontiguousarray(np.concatenate([scene.quats, host["quats"]], 1)),
-                      opacity=np.ascontiguousarray(np.concatenate([scene.opacity, host["opacity"]])),
-                      sh=np.ascontiguousarray(np.concatenate([scene.sh, host["sh"]], 1)),
-                      level=np.concatenate([scene.level, np.full(m, l, np.uint8)]),
-                      s_max=np.concatenate([scene.s_max, np.zeros(m, np.float32)]),
-                      s_min=np.concatenate([scene.s_min, np.full(m, np.inf, np.float32)]))
-    return scene, added
+    n0 = int(scene0.n)
+    K3 = 3 * (scene0.sh_degree + 1) ** 2
+    host = [np.ascontiguousarray(getattr(scene0, k)) for k in DeviceScene.FIELDS]
+    base = SceneDesc(n0, int(scene0.sh_degree), int(n_levels), *[a.ctypes.data for a in host], 0)
+    arr = (CameraC * len(cams))(*[camera_c(c) for c in cams])
+    added = (C.c_int64 * max(1, n_levels - 1))()
+    cap = 2 * n0 + 1024
+    dev = torch.device("cuda", ctx.device)
+    while True:
+        out = {"means": torch.empty((3, cap), device=dev), "scales": torch.empty((3, cap), device=dev),
+               "quats": torch.empty((4, cap), device=dev), "opacity": torch.empty(cap, device=dev),
+               "sh": torch.empty((K3, cap), device=dev),
+               "level": torch.empty(cap, dtype=torch.uint8, device=dev),
+               "s_max": torch.empty(cap, device=dev), "s_min": torch.empty(cap, device=dev)}
+        so = SceneOut(*[out[k].data_ptr() for k in DeviceScene.FIELDS], cap)
+        n_out = C.c_int64()
+        rc = lib().msgs_build_levels(ctx.h, C.byref(base), arr, len(cams), int(n_levels),
+                                     float(s_thresh), C.byref(so), C.byref(n_out), added,
+                                     C.c_void_p(_stream()))
+        if rc == E_CAPACITY:
+            cap = max(2 * cap, 2 * n_out.value)
+            continue
+        check(rc)
+        break
+    m = n_out.value
+    h = {k: out[k][..., :m].cpu().numpy() for k in DeviceScene.FIELDS}
+    scene = Scene(n=m, sh_degree=scene0.sh_degree, n_levels=n_levels,
+                  **{k: np.ascontiguousarray(h[k]) for k in DeviceScene.FIELDS})
+    return scene, [int(added[i]) for i in range(n_levels - 1)]

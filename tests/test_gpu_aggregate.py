@@ -54,11 +54,21 @@ def test_multilevel_build_matches_oracle(ctx):
         part = _compare_level(ctx, scene, cams, l)
         part = dataclasses.replace(part, n_levels=4)
         scene = A.concat(scene, part)
-    # the library's own end-to-end build gives the same level sizes here
+    # the library's own end-to-end build (msgs_build_levels: defaults, level
+    # loop and concatenation on the device) gives the oracle's level sizes; the
+    # first level's Gaussians match the oracle's and the base is copied through
     full, added = M.build_levels(ctx, sc, cams, 4)
-    _, ref_added = A.build_levels(sc, cams, 4)
+    ref_full, ref_added = A.build_levels(sc, cams, 4)
     assert added[0] == ref_added[0]
     assert full.n == sc.n + sum(added)
+    np.testing.assert_array_equal(full.means[:, :sc.n], sc.means)
+    np.testing.assert_array_equal(full.level[:sc.n], sc.level)
+    lv1 = slice(sc.n, sc.n + added[0])
+    np.testing.assert_array_equal(full.level[lv1], 1)
+    assert np.all(full.s_max[lv1] == 0) and np.all(np.isinf(full.s_min[lv1]))
+    for k in NAMES:
+        np.testing.assert_allclose(getattr(full, k)[..., lv1], getattr(ref_full, k)[..., lv1],
+                                   rtol=2e-5, atol=2e-6, err_msg=k)
 
 
 def test_full_size_level0_of_the_four_level_scene(ctx):
@@ -78,13 +88,18 @@ def test_capacity_and_invalid_arguments(ctx):
     g = M.Gaussians(*[t.data_ptr() for t in outs], 2)
     arr = (M.CameraC * len(cams))(*[M.camera_c(c) for c in cams])
     n_out = C.c_int64()
-    B = M.camera_extent(cams)
+    B = float(A.scene_extent(cams))
     rc = M.lib().msgs_aggregate_level(ctx.h, dsc.h, arr, len(cams), 1, 2.0, B, 200, C.byref(g),
                                       C.byref(n_out), None)
     assert rc == M.E_CAPACITY and n_out.value > 2
     ref, _, _ = A.aggregate_level(sc, cams, 1, 2.0, B)
     assert n_out.value == ref.n
-    for bad in ((0, 200), (3, 200), (1, 0), (1, 256)):
+    # 0 selects the library's defaults (S_T = 2, the cameras' extent, 400 / 2
+    # voxels at level 1): the same count as the explicit values
+    rc = M.lib().msgs_aggregate_level(ctx.h, dsc.h, arr, len(cams), 1, 0.0, 0.0, 0, C.byref(g),
+                                      C.byref(n_out), None)
+    assert rc == M.E_CAPACITY and n_out.value == ref.n
+    for bad in ((0, 200), (3, 200), (1, -1), (1, 256)):
         rc = M.lib().msgs_aggregate_level(ctx.h, dsc.h, arr, len(cams), bad[0], 2.0, B, bad[1],
                                           C.byref(g), C.byref(n_out), None)
         assert rc == M.E_INVALID, bad
