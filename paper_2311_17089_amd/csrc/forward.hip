@@ -397,8 +397,11 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
   uint32_t visits = inside ? rg.y - rg.x : 0u;  // replaced by the stop position on termination
   bool done = !inside;
   const unsigned long long lt = __lanemask_lt();
-  // gathers of chunk c + 1 are in flight while chunk c is composited (plain
-  // float4 registers: an aggregate here would be promoted to LDS)
+  // the list is read two chunks ahead: while chunk c is composited, the
+  // records of chunk c + 1 (whose list entries arrived one chunk earlier) and
+  // the list entries of chunk c + 2 are in flight, so a chunk waits for one
+  // memory round trip, not for the two of the entry -> record indirection
+  // (plain float4 registers: an aggregate here would be promoted to LDS)
   float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
   // windows start at multiples of 64 in the list when boundaries are stored
   const uint32_t cfirst = ckpt ? rg.x & ~63u : rg.x;
@@ -409,6 +412,8 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
     n1 = rp->r1;
     n2 = rp->r2;
   }
+  uint32_t tnext = 0u;  // list entry of this lane in the next chunk
+  if (cfirst + 64 + lane < rg.y) tnext = tvals[cfirst + 64 + lane];
   const uint32_t lmask = (1u << lshift) - 1u;
   for (uint32_t c0 = cfirst; c0 < rg.y && __any(!done); c0 += 64) {
     if (ckpt && c0 > rg.x && (c0 & lmask) == 0u) {
@@ -447,11 +452,12 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
     const uint32_t nidx = c0 + 64 + lane;
     have = nidx < rg.y;
     if (have) {
-      const Rec* rp = rec + tvals[nidx];
+      const Rec* rp = rec + tnext;
       n0 = rp->r0;
       n1 = rp->r1;
       n2 = rp->r2;
     }
+    if (nidx + 64 < rg.y) tnext = tvals[nidx + 64];
     // branch-free compositing, four instances per step: evaluated
     // independently, composited in order with selects; a lane that is done
     // adds exactly zero (C + c * 0 = C, T unchanged)
