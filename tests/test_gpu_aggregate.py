@@ -104,3 +104,53 @@ def test_capacity_and_invalid_arguments(ctx):
                                           C.byref(g), C.byref(n_out), None)
         assert rc == M.E_INVALID, bad
     dsc.close()
+
+
+def _build_raw(ctx, scene0, cams, n_levels, cap, s_thresh=0.0):
+    """One msgs_build_levels call into `cap`-pitch device planes."""
+    K3 = 3 * (scene0.sh_degree + 1) ** 2
+    host = [np.ascontiguousarray(getattr(scene0, k)) for k in M.DeviceScene.FIELDS]
+    base = M.SceneDesc(int(scene0.n), int(scene0.sh_degree), int(n_levels),
+                       *[a.ctypes.data for a in host], 0)
+    arr = (M.CameraC * max(1, len(cams)))(*[M.camera_c(c) for c in cams])
+    added = (C.c_int64 * max(1, n_levels - 1))()
+    dev = torch.device("cuda", ctx.device)
+    shapes = {"means": (3, cap), "scales": (3, cap), "quats": (4, cap), "opacity": (cap,),
+              "sh": (K3, cap), "s_max": (cap,), "s_min": (cap,)}
+    out = {k: torch.full(shp, -7.0, device=dev) for k, shp in shapes.items()}
+    out["level"] = torch.full((cap,), 99, dtype=torch.uint8, device=dev)
+    so = M.SceneOut(*[out[k].data_ptr() for k in M.DeviceScene.FIELDS], cap)
+    n_out = C.c_int64(-1)
+    rc = M.lib().msgs_build_levels(ctx.h, C.byref(base), arr, len(cams), int(n_levels),
+                                   float(s_thresh), C.byref(so), C.byref(n_out), added, None)
+    torch.cuda.synchronize()
+    return rc, n_out.value, [int(added[i]) for i in range(max(0, n_levels - 1))], out
+
+
+def test_build_levels_edge_cases(ctx):
+    sc = G.make_scene([3000], 5, 1, [-4.6])
+    cams = G.calibration_cameras(1005, 320, 240, 300.0)
+    # one level: the base is copied through unchanged and nothing is added
+    rc, n, added, out = _build_raw(ctx, sc, cams, 1, sc.n + 10)
+    assert rc == M.OK and n == sc.n and added == []
+    for k in M.DeviceScene.FIELDS:
+        np.testing.assert_array_equal(out[k][..., :sc.n].cpu().numpy(), getattr(sc, k), err_msg=k)
+    # the rest of the planes is left as it was
+    assert np.all(out["opacity"][sc.n:].cpu().numpy() == -7.0)
+    # an output that cannot hold the base: capacity error with the size needed
+    rc, n, _, _ = _build_raw(ctx, sc, cams, 3, sc.n - 1)
+    assert rc == M.E_CAPACITY and n == sc.n
+    # an output that holds the base but not the new levels: capacity error,
+    # and the size needed up to the level that did not fit
+    full, ref_added = A.build_levels(sc, cams, 3)
+    assert ref_added[0] > 0
+    rc, n, _, _ = _build_raw(ctx, sc, cams, 3, sc.n)
+    assert rc == M.E_CAPACITY and n == sc.n + ref_added[0]
+    # invalid arguments
+    for bad_levels in (0, 9):
+        rc, _, _, _ = _build_raw(ctx, sc, cams, bad_levels, sc.n + 10)
+        assert rc == M.E_INVALID, bad_levels
+    rc, _, _, _ = _build_raw(ctx, sc, [], 2, 2 * sc.n)
+    assert rc == M.E_INVALID
+    rc, _, _, _ = _build_raw(ctx, sc, cams, 2, 2 * sc.n, s_thresh=-1.0)
+    assert rc == M.E_INVALID
