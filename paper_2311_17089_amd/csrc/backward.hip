@@ -357,18 +357,24 @@ __device__ __forceinline__ void store3(float* gsum, int64_t k, const float* s) {
 
 // Per-Gaussian sums of the partials over the emission range, Gaussians in
 // emission order; those with more than kSmallSeg tiles are queued for
-// k_seg_big.  Ranges are clipped to `cap` (the tile lists of a fixed-capacity
-// frame end there, also when the frame overflowed).
-__global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int64_t n_vis,
-                                                      const uint32_t* d_nvis,
-                                                      const uint32_t* count,
-                                                      const uint32_t* emit_base, uint32_t cap,
-                                                      const float* partial, const uint32_t* wmask,
-                                                      float* gsum, uint32_t* big, uint32_t* nbig) {
+// k_seg_big.  A Gaussian's range is [off[j], off[j + 1]) (off: the emission
+// offsets in emission order, the last range ending at the instance total), so
+// neighbouring threads read neighbouring words instead of gathering counts
+// and bases by Gaussian index.  Ranges are clipped to `cap` (the tile lists of
+// a fixed-capacity frame end there, also when the frame overflowed).
+__global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, const uint32_t* off,
+                                                      const unsigned long long* d_total,
+                                                      int64_t n_vis, const uint32_t* d_nvis,
+                                                      uint32_t cap, const float* partial,
+                                                      const uint32_t* wmask, float* gsum,
+                                                      uint32_t* big, uint32_t* nbig) {
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (j >= n_vis || j >= (int64_t)*d_nvis) return;
+  const int64_t nv = min((int64_t)*d_nvis, n_vis);
+  if (j >= nv) return;
   const uint32_t k = order[j];
-  const uint32_t c = count[k];
+  const uint32_t b = off[j];
+  const uint32_t b1 = j + 1 < nv ? off[j + 1] : (uint32_t)*d_total;
+  const uint32_t c = b1 - b;
   if (c > kSmallSeg) {
     big[atomicAdd(nbig, 1u)] = k;
     return;
@@ -377,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_small(const uint32_t* order, int
 #pragma unroll
   for (int q = 0; q < kNP; ++q) s[q] = 0.0f;
   // only the slots whose partial was written (bit set) are read, in order
-  const uint32_t e0 = min(emit_base[k], cap), e1 = min(emit_base[k] + c, cap);
+  const uint32_t e0 = min(b, cap), e1 = min(b1, cap);
   for (uint32_t w0 = e0 & ~31u; w0 < e1; w0 += 32u) {
     uint32_t bits = wmask[w0 >> 5];
     const uint32_t lo = e0 > w0 ? e0 - w0 : 0u;
@@ -738,8 +744,8 @@ static void launch_chain_d(const BwdArgs& a, dim3 g, dim3 b, hipStream_t st) {
 void launch_backward_segsum(const BwdArgs& a, hipStream_t st) {
   if (a.s.n == 0 || a.n_vis == 0) return;
   const uint32_t cap = (uint32_t)std::min<int64_t>(a.n_inst, 0xFFFFFFFFll);
-  hipLaunchKernelGGL(k_seg_small, dim3(grid_for(a.n_vis)), dim3(kBlock), 0, st, a.order, a.n_vis,
-                     a.d_nvis, a.count, a.emit_base, cap, a.partial, a.wmask, a.gsum, a.big,
+  hipLaunchKernelGGL(k_seg_small, dim3(grid_for(a.n_vis)), dim3(kBlock), 0, st, a.order, a.off,
+                     a.d_total, a.n_vis, a.d_nvis, cap, a.partial, a.wmask, a.gsum, a.big,
                      a.nbig);
   hipLaunchKernelGGL(k_seg_big, dim3(1024), dim3(kBlock), 0, st, a.count, a.emit_base, cap,
                      a.partial, a.wmask, a.gsum, a.big, a.nbig);

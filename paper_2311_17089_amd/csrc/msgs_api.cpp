@@ -985,6 +985,8 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   a.rec = f->rec;
   a.rect = f->rect;
   a.emit_base = f->emit_base;
+  a.off = f->off_d;
+  a.d_total = &f->ctr[3];
   a.count = f->count;
   a.order = f->order;
   a.n_vis = f->n_vis;
@@ -1080,11 +1082,13 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
     a.rec = f->rec;
     a.rect = f->rect;
     a.emit_base = f->emit_base;
+    a.off = f->off_d;
+    a.d_total = &f->ctr[3];
     a.count = f->count;
     a.order = f->order;
-      a.n_vis = f->n_vis;
+    a.n_vis = f->n_vis;
     a.d_nvis = (const uint32_t*)&f->ctr[2];
-      a.T_final = f->T_final;
+    a.T_final = f->T_final;
     a.n_last = f->n_last;
     a.dL_drgb = dL_drgb[i];
     a.n_inst = f->n_inst;

@@ -142,6 +142,8 @@ struct BwdArgs {
   const uint32_t* emit_base;
   const uint32_t* count;
   const uint32_t* order;    // drawable Gaussians in depth (emission) order
+  const uint32_t* off;      // their emission offsets, in the same order
+  const unsigned long long* d_total;  // instances the frame needs (device u64)
   int64_t n_vis;            // upper bound of the drawable count
   const uint32_t* d_nvis;   // drawable count on the device
   const float* T_final;
