@@ -347,6 +347,13 @@ __device__ __forceinline__ int xcd_quad(int b, int& quad) {
   return (((cc >> 2) << 3) + (b & 7)) * 4 + (cc & 3);
 }
 
+// Frames of fewer tiles than this composite with four waves per quadrant
+// (k_blend_q4), larger ones with one (k_blend).
+#ifndef MSGS_BLEND_Q4_TILES
+#define MSGS_BLEND_Q4_TILES 128
+#endif
+constexpr int kBlendQ4Tiles = MSGS_BLEND_Q4_TILES;
+
 // One single-wave workgroup per 8x8 quadrant of a 16x16 tile: the wave walks
 // the tile's list on its own, 64 instances at a time (a finished quadrant
 // frees its slot at once, whatever the rest of the tile does).  Each lane gathers one record; a ballot keeps the instances whose
@@ -545,6 +552,205 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
   if (lane == 0 && e64) atomicAdd(sl + 3, e64);
 }
 
+// The same compositing with four waves per 8x8 quadrant, for frames of few
+// tiles: there one wave per quadrant is one long dependency chain with the
+// rest of the chip idle.  Wave 0 walks the list as k_blend does (gathers two
+// chunks ahead, culls a chunk to the quadrant, packs the hits into LDS, stores
+// the replay checkpoints) and composites; between the cull and the
+// compositing all four waves evaluate the hits' alpha for the 64 pixels
+// (wave w takes hits w, w + 4, ...) into an LDS table, so that wave 0's
+// compositing is the short sequential part only.  Every value is computed by
+// the same operations in the same order as in k_blend, so images, counts and
+// checkpoints are bit-identical to it.
+__global__ __launch_bounds__(kBlock) void k_blend_q4(const uint2* ranges, const uint32_t* tvals,
+                                                     const Rec* rec, ViewParams v, int ntile,
+                                                     float* rgb, float* T_final,
+                                                     uint32_t* n_accum, uint32_t* n_last,
+                                                     unsigned long long* slots, float4* ckpt,
+                                                     int lshift) {
+  __shared__ float4 s0[64], s1[64], s2[64];
+  __shared__ uint32_t spos[64];
+  __shared__ float sa[64][64];  // alpha of hit i at pixel (lane), -1 when it is not taken
+  __shared__ int s_nl;          // hits of the current chunk, -1 when the walk is over
+  int quad;
+  const int tile = xcd_quad(blockIdx.x, quad);
+  if (tile >= ntile) return;  // workgroup-uniform
+  const int tx = tile % v.Tx, ty = tile / v.Tx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int qx = tx * kTile + (quad & 1) * 8, qy = ty * kTile + (quad >> 1) * 8;
+  const int px = qx + (lane & 7);
+  const int py = qy + (lane >> 3);
+  const bool inside = px < v.W && py < v.H;
+  const float pcx = (float)px + 0.5f;
+  const float pcy = (float)py + 0.5f;
+  const float bx0 = (float)qx + 0.5f, bx1 = (float)qx + 7.5f;
+  const float by0 = (float)qy + 0.5f, by1 = (float)qy + 7.5f;
+  const uint2 rg = ranges[tile];
+  // wave 0's per-pixel state (the other waves only evaluate alphas)
+  float T = 1.0f;
+  float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+  float Cb0 = 0.0f, Cb1 = 0.0f, Cb2 = 0.0f;
+  uint32_t nbd = 0, fbd = 0;
+  uint32_t cnt = 0, last = 0, wev = 0;
+  uint32_t visits = inside ? rg.y - rg.x : 0u;
+  bool done = !inside;
+  const unsigned long long lt = __lanemask_lt();
+  float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0, n2 = n0;
+  const uint32_t cfirst = ckpt ? rg.x & ~63u : rg.x;
+  bool have = false;
+  uint32_t tnext = 0u;
+  if (wave == 0) {
+    have = cfirst + lane >= rg.x && cfirst + lane < rg.y;
+    if (have) {
+      const Rec* rp = rec + tvals[cfirst + lane];
+      n0 = rp->r0;
+      n1 = rp->r1;
+      n2 = rp->r2;
+    }
+    if (cfirst + 64 + lane < rg.y) tnext = tvals[cfirst + 64 + lane];
+  }
+  const uint32_t lmask = (1u << lshift) - 1u;
+  for (uint32_t c0 = cfirst;; c0 += 64) {
+    if (wave == 0) {
+      int nl = -1;
+      if (c0 < rg.y && __any(!done)) {
+        if (ckpt && c0 > rg.x && (c0 & lmask) == 0u) {
+          ckpt[(size_t)(c0 >> lshift) * (kTile * kTile) + quad * 64 + lane] =
+              make_float4(C0, C1, C2, T);
+          if (nbd == 0) fbd = c0 >> lshift;
+          ++nbd;
+          Cb0 += C0;
+          Cb1 += C1;
+          Cb2 += C2;
+          C0 = C1 = C2 = 0.0f;
+        }
+        const bool hit = have && !(n0.x + n2.z < bx0 || n0.x - n2.z > bx1 || n0.y + n2.w < by0 ||
+                                   n0.y - n2.w > by1) &&
+                         level_set_meets_box(n0.x, n0.y, n0.z, n0.w, n1.x, -n1.z, bx0, bx1, by0,
+                                             by1);
+        const unsigned long long m = __ballot(hit);
+        nl = __popcll(m);
+        if (hit) {
+          const int q = __popcll(m & lt);
+          s0[q] = n0;
+          s1[q] = n1;
+          s2[q] = n2;
+          spos[q] = c0 + (uint32_t)lane + 1 - rg.x;
+        }
+        if (lane >= nl && lane < nl + 3) {  // finite padding read by the compositing
+          const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          s0[lane] = z;
+          s1[lane] = z;
+          s2[lane] = z;
+          spos[lane] = 0u;
+        }
+        const uint32_t nidx = c0 + 64 + lane;
+        have = nidx < rg.y;
+        if (have) {
+          const Rec* rp = rec + tnext;
+          n0 = rp->r0;
+          n1 = rp->r1;
+          n2 = rp->r2;
+        }
+        if (nidx + 64 < rg.y) tnext = tvals[nidx + 64];
+      }
+      if (lane == 0) s_nl = nl;
+    }
+    __syncthreads();
+    const int nl = s_nl;
+    if (nl < 0) break;  // workgroup-uniform
+    // alpha of every hit at every pixel, hits dealt round-robin to the waves
+    for (int j = wave; j < nl; j += 4) {
+      const float4 a = s0[j];
+      const float4 b = s1[j];
+      const float dx = pcx - a.x;
+      const float dy = pcy - a.y;
+      const float qxx = dx * dx, qyy = dy * dy, qxy = dx * dy;
+      const float e = -0.5f * (a.z * qxx + b.x * qyy);
+      const float power = e - a.w * qxy;
+      const float ar = b.y * exp_c(power);
+      const bool pre = !(power > 0.0f) && !(power < b.z) && !(ar < kAlphaMin);
+      sa[j][lane] = pre ? ar : -1.0f;  // a taken alpha is kAlphaMin or more (or NaN)
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // sequential compositing, four hits per step as in k_blend
+      int i = 0;
+      for (; i < nl; i += 4) {
+        float ar[4];
+        bool pre[4];
+        float4 cb[4];
+        uint32_t p1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = min(i + u, 63);
+          ar[u] = i + u < nl ? sa[j][lane] : -1.0f;
+          pre[u] = !(ar[u] < 0.0f);
+          cb[u] = make_float4(s1[j].w, s2[j].x, s2[j].y, 0.0f);
+          p1[u] = spos[j];
+        }
+        bool any_stop = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool ok = pre[u] && !done;
+          const float al = fminf(kAlphaMax, ar[u]);
+          const float Tn = T * (1.0f - al);
+          const bool stop = ok && Tn < kTMin;
+          const bool acc = ok && !stop;
+          const float w = acc ? al * T : 0.0f;
+          C0 = fmaf(cb[u].x, w, C0);
+          C1 = fmaf(cb[u].y, w, C1);
+          C2 = fmaf(cb[u].z, w, C2);
+          T = acc ? Tn : T;
+          cnt += acc ? 1u : 0u;
+          last = acc ? p1[u] : last;
+          visits = stop ? p1[u] : visits;
+          done = done || stop;
+          any_stop = any_stop || stop;
+        }
+        if (__any(any_stop) && __all(done)) {  // both votes are wave-uniform
+          i += 4;
+          break;
+        }
+      }
+      wev += (uint32_t)min(i, nl);
+    }
+    // the next chunk's cull overwrites the hit records only after every
+    // wave has passed the barrier at the top of the next iteration
+  }
+  if (wave != 0) return;
+  if (inside) {
+    const int64_t pix = (int64_t)py * v.W + px;
+    rgb[pix * 3 + 0] = (Cb0 + C0) + T * v.bg[0];
+    rgb[pix * 3 + 1] = (Cb1 + C1) + T * v.bg[1];
+    rgb[pix * 3 + 2] = (Cb2 + C2) + T * v.bg[2];
+    T_final[pix] = T;
+    n_accum[pix] = cnt;
+    n_last[pix] = last;
+  }
+  float S0 = C0, S1 = C1, S2 = C2;
+  for (uint32_t m = nbd; m > 0; --m) {
+    float4* cp = ckpt + (size_t)(fbd + m - 1) * (kTile * kTile) + quad * 64 + lane;
+    const float4 o = *cp;
+    *cp = make_float4(S0, S1, S2, o.w);
+    S0 += o.x;
+    S1 += o.y;
+    S2 += o.z;
+  }
+  unsigned long long c64 = cnt, v64 = visits;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    c64 += __shfl_xor(c64, o, 64);
+    v64 += __shfl_xor(v64, o, 64);
+  }
+  const unsigned long long e64 =
+      (unsigned long long)wev * (unsigned long long)__popcll(__ballot(inside));
+  unsigned long long* sl = slots + (blockIdx.x % kCtrSlots) * kSlotW;
+  if (lane == 0 && c64) atomicAdd(sl + 1, c64);
+  if (lane == 0 && v64) atomicAdd(sl + 2, v64);
+  if (lane == 0 && e64) atomicAdd(sl + 3, e64);
+}
+
 __global__ __launch_bounds__(kBlock) void k_debug_exp(const float* x, float* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) y[i] = exp_c(x[i]);
@@ -666,8 +872,12 @@ void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, co
                   unsigned long long* slots, float4* ckpt, int lshift, hipStream_t st) {
   const int ntile = v.Tx * v.Ty;
   const int nblk = (ntile + 31) / 32 * 32 * 4;
-  hipLaunchKernelGGL(k_blend, dim3(nblk), dim3(64), 0, st, ranges, tvals, rec, v, ntile, rgb,
-                     T_final, n_accum, n_last, slots, ckpt, lshift);
+  if (ntile < kBlendQ4Tiles)
+    hipLaunchKernelGGL(k_blend_q4, dim3(nblk), dim3(kBlock), 0, st, ranges, tvals, rec, v, ntile,
+                       rgb, T_final, n_accum, n_last, slots, ckpt, lshift);
+  else
+    hipLaunchKernelGGL(k_blend, dim3(nblk), dim3(64), 0, st, ranges, tvals, rec, v, ntile, rgb,
+                       T_final, n_accum, n_last, slots, ckpt, lshift);
 }
 
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st) {
