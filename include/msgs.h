@@ -233,8 +233,9 @@ int msgs_render_views(msgs_context* ctx, msgs_scene* scene, const msgs_camera* c
  * calls no hipMalloc, hipFree or other allocating routine.
  *   opts->instance_capacity  0: as many tile instances as fit in the scratch
  *                (about (256 MiB - per-Gaussian and per-pixel buffers) / 16
- *                bytes for frames of 128 tiles or more; smaller frames also
- *                keep replay checkpoints, 64 bytes per instance); > 0: that
+ *                bytes; frames of fewer than 128 tiles also keep replay
+ *                checkpoints, 64 bytes per instance, and frames of a scene
+ *                with more than 8192 Gaussians per tile 4 bytes); > 0: that
  *                capacity, MSGS_E_CAPACITY if it does not fit
  *   counts_out   optional device u64[3]: drawable Gaussians, tile instances the
  *                frame needs, instances that fit (the image is complete when

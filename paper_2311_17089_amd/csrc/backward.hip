@@ -321,6 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
                                                       int ntile, const float* T_final,
                                                       const uint32_t* n_last, const float* dLdC,
                                                       const float4* ckpt, int lshift,
+                                                      const uint32_t* tmax,
                                                       const uint32_t* d_inst, uint32_t ninst_max,
                                                       float* partial, uint32_t* wmask) {
   __shared__ BwdShared sh;
@@ -341,8 +342,11 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const uint2* ranges, const
     const int tile = (int)tkeys[p];
     const uint2 rg = ranges[tile];
     const uint32_t seg1 = min(rg.y, pend);
-    replay_segment(sh, tile, rg, p, seg1, tvals, rec, rect, emit_base, v, T_final, n_last, dLdC,
-                   ckpt, lshift, partial, wmask);
+    // a segment that starts at or past every pixel's last contributor holds
+    // no contribution (its instances' partials are zero and stay unwritten)
+    if (p - rg.x < tmax[tile])
+      replay_segment(sh, tile, rg, p, seg1, tvals, rec, rect, emit_base, v, T_final, n_last,
+                     dLdC, ckpt, lshift, partial, wmask);
     p = seg1;
     __syncthreads();  // the next segment rewrites smax and the LDS batch
   }
@@ -719,13 +723,14 @@ void launch_backward_blend(const BwdArgs& a, hipStream_t st) {
     const int64_t nblk = replay_blocks(a.n_inst, a.lshift);
     hipLaunchKernelGGL(k_blend_bwd<true>, dim3((unsigned)nblk), dim3(kBlock), 0, st, a.ranges,
                        a.tkeys, a.tvals, a.rec, a.rect, a.emit_base, a.v, ntile, a.T_final,
-                       a.n_last, a.dL_drgb, a.ckpt, a.lshift, a.d_inst, (uint32_t)a.n_inst,
-                       a.partial, a.wmask);
+                       a.n_last, a.dL_drgb, a.ckpt, a.lshift, a.tmax, a.d_inst,
+                       (uint32_t)a.n_inst, a.partial, a.wmask);
   } else {
     const int nblk = (ntile + 31) / 32 * 32;
     hipLaunchKernelGGL(k_blend_bwd<false>, dim3(nblk), dim3(kBlock), 0, st, a.ranges, a.tkeys,
                        a.tvals, a.rec, a.rect, a.emit_base, a.v, ntile, a.T_final, a.n_last,
-                       a.dL_drgb, a.ckpt, 0, a.d_inst, (uint32_t)a.n_inst, a.partial, a.wmask);
+                       a.dL_drgb, a.ckpt, 0, a.tmax, a.d_inst, (uint32_t)a.n_inst, a.partial,
+                       a.wmask);
   }
 }
 

@@ -379,7 +379,7 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
                                                   float* rgb, float* T_final, uint32_t* n_accum,
                                                   uint32_t* n_last,
                                                   unsigned long long* slots, float4* ckpt,
-                                                  int lshift) {
+                                                  int lshift, uint32_t* tmax) {
   __shared__ float4 s0[64], s1[64], s2[64];
   __shared__ uint32_t spos[64];
   int quad;
@@ -536,6 +536,13 @@ __global__ __launch_bounds__(64) void k_blend(const uint2* ranges, const uint32_
     S1 += o.y;
     S2 += o.z;
   }
+  if (ckpt) {
+    // the tile's largest contributor count, for the backward's block skip
+    uint32_t wl = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wl = max(wl, (uint32_t)__shfl_xor((int)wl, o, 64));
+    if (lane == 0 && wl) atomicMax(tmax + tile, wl);
+  }
   // per-wave counts, added to one of kCtrSlots counter slots (atomics on a
   // single address from every wave would serialise at the memory side)
   unsigned long long c64 = cnt, v64 = visits;
@@ -567,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_q4(const uint2* ranges, const 
                                                      float* rgb, float* T_final,
                                                      uint32_t* n_accum, uint32_t* n_last,
                                                      unsigned long long* slots, float4* ckpt,
-                                                     int lshift) {
+                                                     int lshift, uint32_t* tmax) {
   __shared__ float4 s0[64], s1[64], s2[64];
   __shared__ uint32_t spos[64];
   __shared__ float sa[64][64];  // alpha of hit i at pixel (lane), -1 when it is not taken
@@ -737,6 +744,13 @@ __global__ __launch_bounds__(kBlock) void k_blend_q4(const uint2* ranges, const 
     S1 += o.y;
     S2 += o.z;
   }
+  if (ckpt) {
+    // the tile's largest contributor count, for the backward's block skip
+    uint32_t wl = last;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wl = max(wl, (uint32_t)__shfl_xor((int)wl, o, 64));
+    if (lane == 0 && wl) atomicMax(tmax + tile, wl);
+  }
   unsigned long long c64 = cnt, v64 = visits;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -869,15 +883,16 @@ void launch_ranges(const uint32_t* tkeys, const uint32_t* d_n, uint32_t nmax, ui
 
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* slots, float4* ckpt, int lshift, hipStream_t st) {
+                  unsigned long long* slots, float4* ckpt, int lshift, uint32_t* tmax,
+                  hipStream_t st) {
   const int ntile = v.Tx * v.Ty;
   const int nblk = (ntile + 31) / 32 * 32 * 4;
   if (ntile < kBlendQ4Tiles)
     hipLaunchKernelGGL(k_blend_q4, dim3(nblk), dim3(kBlock), 0, st, ranges, tvals, rec, v, ntile,
-                       rgb, T_final, n_accum, n_last, slots, ckpt, lshift);
+                       rgb, T_final, n_accum, n_last, slots, ckpt, lshift, tmax);
   else
     hipLaunchKernelGGL(k_blend, dim3(nblk), dim3(64), 0, st, ranges, tvals, rec, v, ntile, rgb,
-                       T_final, n_accum, n_last, slots, ckpt, lshift);
+                       T_final, n_accum, n_last, slots, ckpt, lshift, tmax);
 }
 
 void launch_debug_exp(const float* x, float* y, int64_t n, hipStream_t st) {

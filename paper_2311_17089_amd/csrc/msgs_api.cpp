@@ -161,7 +161,7 @@ void phase1_layout(msgs_frame* f, Carve& keep, Carve& tmp) {
   keep.add(&f->rec, n * sizeof(Rec));
   keep.add(&f->rect, n * sizeof(uint2));
   keep.add(&f->emit_base, n * 4);
-  keep.add(&f->ranges, (size_t)ntile * sizeof(uint2));
+  keep.add(&f->ranges, (size_t)ntile * (sizeof(uint2) + 4));  // ranges, then tmax
   keep.add(&f->T_final, P * 4);
   keep.add(&f->n_accum, P * 4);
   keep.add(&f->n_last, P * 4);
@@ -187,7 +187,8 @@ void phase1_zero(msgs_frame* f) {
   const int64_t nb = (n + kBlock - 1) / kBlock;
   ZeroList z;
   z.add(f->ctr, 2 * (8 + kSlotW * kCtrSlots));
-  z.add(f->ranges, (int64_t)ntile * 2);  // tiles with no instance keep (0, 0)
+  f->tmax = (uint32_t*)(f->ranges + ntile);
+  z.add(f->ranges, (int64_t)ntile * 3);  // tiles with no instance keep (0, 0); tmax 0
   z.add(f->scan_tmp2, scan_zero_words(n));
   z.add(f->sort_tmp, radix_zero_words(n, radix_passes(0, 32)));
   if (nb > kCompactInKernelBlocks) z.add(f->cscan_tmp, scan_zero_words(nb));
@@ -246,7 +247,7 @@ int render_phase1(msgs_frame* f) {
 void phase2_layout(msgs_frame* f, Carve& keep, Carve& tmp, Phase2Bufs& b) {
   const int64_t I = f->n_inst;
   const int bits = tile_bits(f->v.Tx * f->v.Ty);
-  f->lshift = replay_block_shift(f->v.Tx * f->v.Ty);
+  f->lshift = replay_block_shift(f->v.Tx * f->v.Ty, f->n);
   keep.add(&b.ka, I * 4);
   keep.add(&b.va, I * 4);
   if (f->lshift > 0)
@@ -289,7 +290,7 @@ void phase2_launch(msgs_frame* f, float* rgb_out, const Phase2Bufs& b) {
   launch_ranges(f->tkeys, d_inst, (uint32_t)I, f->ranges, st);
   mark(f, 7);
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
-               f->ctr + 8, f->ckpt, f->lshift, st);
+               f->ctr + 8, f->ckpt, f->lshift, f->tmax, st);
   mark(f, 8);
 }
 
@@ -980,6 +981,7 @@ int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_d
   a.tkeys = f->tkeys;
   a.tvals = f->tvals;
   a.ckpt = f->ckpt;
+  a.tmax = f->tmax;
   a.lshift = f->lshift;
   a.d_inst = f->capacity ? (const uint32_t*)&f->ctr[7] : nullptr;
   a.rec = f->rec;
@@ -1077,6 +1079,7 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
     a.tkeys = f->tkeys;
     a.tvals = f->tvals;
     a.ckpt = f->ckpt;
+    a.tmax = f->tmax;
     a.lshift = f->lshift;
     a.d_inst = f->capacity ? (const uint32_t*)&f->ctr[7] : nullptr;
     a.rec = f->rec;

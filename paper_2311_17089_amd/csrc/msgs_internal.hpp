@@ -94,6 +94,8 @@ struct msgs_frame {
   uint2* rect = nullptr;
   uint32_t* emit_base = nullptr;
   uint2* ranges = nullptr;
+  uint32_t* tmax = nullptr;           // per tile, its pixels' largest contributor count
+                                      // (written when replay checkpoints are kept)
   float* T_final = nullptr;
   uint32_t* n_accum = nullptr;
   uint32_t* n_last = nullptr;

@@ -77,21 +77,33 @@ void launch_ranges(const uint32_t* tkeys, const uint32_t* d_n, uint32_t nmax, ui
 // tile, per pixel the suffix colour from the boundary on and the transmittance
 // before it, for the backward (block length 2^lshift >= 64; see
 // replay_block_shift)
+// tmax (with ckpt): per tile, the largest contributor count of its pixels
+// (zeroed by the caller), which lets the backward skip blocks past it
 void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, const ViewParams& v,
                   float* rgb, float* T_final, uint32_t* n_accum, uint32_t* n_last,
-                  unsigned long long* slots, float4* ckpt, int lshift, hipStream_t st);
-// log2 of the backward replay's block length for a frame of ntile tiles, or 0
-// for a replay with one workgroup per tile.  Frames of 128 tiles and more keep
-// one workgroup per tile (enough workgroups, and an XCD-aware tile order whose
-// L2s share the records of neighbouring tiles: measured on a 425-tile frame,
-// 68 us against 84-95 us for blocks of 128-512 positions).  Frames of fewer
-// tiles have long lists that one workgroup per tile replays one entry after
-// another, so their lists are cut into blocks of 64 positions, one workgroup
-// each (35- and 2-tile frames: 60 -> 39 us and 71 -> 24 us).  It depends on
-// the frame's size only, not on its instance count, so that a fixed-capacity
-// render composites exactly as the exact-count render of the same view (the
-// colour is summed per block).
-inline int replay_block_shift(int ntile) { return ntile >= 128 ? 0 : 6; }
+                  unsigned long long* slots, float4* ckpt, int lshift, uint32_t* tmax,
+                  hipStream_t st);
+// log2 of the backward replay's block length for a frame of ntile tiles of a
+// scene of n Gaussians, or 0 for a replay with one workgroup per tile.
+// Frames of fewer than 128 tiles have long lists that one workgroup per tile
+// replays one entry after another, so their lists are cut into blocks of 64
+// positions, one workgroup each (35- and 2-tile frames: 60 -> 39 us and 71
+// -> 24 us).  Larger frames keep one workgroup per tile (enough workgroups,
+// and an XCD-aware tile order whose L2s share the records of neighbouring
+// tiles: measured on a 425-tile frame of 531,250 Gaussians, 68 us against
+// 84-95 us for blocks of 128-512 positions) unless the scene has more than
+// 8192 Gaussians per tile: such frames (a 6M-Gaussian scene at 480x270 and
+// 240x135, 510 and 135 tiles) build lists of tens of thousands of instances
+// per tile, and get blocks of 1024 positions (4 bytes of checkpoints per
+// instance); blocks past every pixel's last contributor of their tile return
+// at once.  The block
+// length depends on the frame's size and the scene's, not on the instance
+// count, so that a fixed-capacity render composites exactly as the
+// exact-count render of the same view (the colour is summed per block).
+inline int replay_block_shift(int ntile, int64_t n) {
+  if (ntile < 128) return 6;
+  return n > (int64_t)8192 * ntile ? 10 : 0;
+}
 inline int64_t replay_blocks(int64_t n_inst, int lshift) {
   return lshift > 0 ? (n_inst + ((int64_t)1 << lshift) - 1) >> lshift : 0;
 }
@@ -135,6 +147,7 @@ struct BwdArgs {
   const uint32_t* tkeys;    // sorted tile ids (the tile of every list position)
   const uint32_t* tvals;
   const float4* ckpt;       // suffix colour and transmittance at every replay-block boundary
+  const uint32_t* tmax;     // per tile, largest contributor count (with ckpt)
   int lshift;               // replay block length 2^lshift
   const uint32_t* d_inst;   // instances in the list on the device (fixed capacity), or null
   const Rec* rec;

@@ -106,7 +106,7 @@ extern "C" int msgs_render_noalloc(msgs_context* c, msgs_scene* s, const msgs_ca
     // as many tile instances as fit: 16 bytes each (keys and values, two
     // buffers), the replay checkpoints (256 pixels x 16 bytes per block of
     // 2^lshift instances) and the sort's per-tile words
-    const int lshift = replay_block_shift(v.Tx * v.Ty);
+    const int lshift = replay_block_shift(v.Tx * v.Ty, f.n);
     const double per_inst =
         16.0 + (lshift > 0 ? (double)(kTile * kTile * 16) / (double)(1ll << lshift) : 0.0);
     I = std::min<int64_t>((int64_t)((double)(cap_bytes - fixed) / per_inst), 0xFFFFFFFFll);
