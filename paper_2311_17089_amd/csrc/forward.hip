@@ -348,7 +348,8 @@ __device__ __forceinline__ int xcd_quad(int b, int& quad) {
 }
 
 // Frames of fewer tiles than this composite with four waves per quadrant
-// (k_blend_q4), larger ones with one (k_blend).
+// (k_blend_q4), larger ones with one (k_blend) unless their lists are very
+// long (see launch_blend).
 #ifndef MSGS_BLEND_Q4_TILES
 #define MSGS_BLEND_Q4_TILES 128
 #endif
@@ -887,7 +888,9 @@ void launch_blend(const uint2* ranges, const uint32_t* tvals, const Rec* rec, co
                   hipStream_t st) {
   const int ntile = v.Tx * v.Ty;
   const int nblk = (ntile + 31) / 32 * 32 * 4;
-  if (ntile < kBlendQ4Tiles)
+  // four waves per quadrant for frames of few tiles and for those whose scene
+  // has very many Gaussians per tile (1024-position replay blocks): long walks
+  if (ntile < kBlendQ4Tiles || lshift >= 10)
     hipLaunchKernelGGL(k_blend_q4, dim3(nblk), dim3(kBlock), 0, st, ranges, tvals, rec, v, ntile,
                        rgb, T_final, n_accum, n_last, slots, ckpt, lshift, tmax);
   else
