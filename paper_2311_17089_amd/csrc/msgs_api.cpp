@@ -294,24 +294,38 @@ void phase2_launch(msgs_frame* f, float* rgb_out, const Phase2Bufs& b) {
   mark(f, 8);
 }
 
-int render_phase2(msgs_frame* f, float* rgb_out) {
+// The second phase's buffers, taken on stream st: the kept ones join the
+// frame, the temporaries' block is returned in *tmp_block.
+int phase2_alloc(msgs_frame* f, Phase2Bufs& b, void** tmp_block, hipStream_t st) {
   Carve keep, tmp;
-  Phase2Bufs b;
   phase2_layout(f, keep, tmp, b);
-  int rc = keep.alloc(f->ctx, f->st);
+  int rc = keep.alloc(f->ctx, st);
   if (rc != MSGS_OK) return rc;
   f->blocks.push_back(keep.base);
-  rc = tmp.alloc(f->ctx, f->st);
+  rc = tmp.alloc(f->ctx, st);
   if (rc != MSGS_OK) return rc;
-  phase2_launch(f, rgb_out, b);
-  hipStream_t st = f->st;
-  f->ctx->cache.free(f->ctx, tmp.base, st);
+  *tmp_block = tmp.base;
+  return MSGS_OK;
+}
+
+// Returns both phases' temporaries to the cache on stream st.
+void release_temporaries(msgs_frame* f, void* phase2_tmp, hipStream_t st) {
+  f->ctx->cache.free(f->ctx, phase2_tmp, st);
   f->ctx->cache.free(f->ctx, f->tmp_block, st);
   f->tmp_block = nullptr;
   f->blk_vis = f->blk_pre = f->dvals[0] = f->dvals[1] = nullptr;
   f->cscan_tmp = nullptr;
   f->dkeys[0] = f->dkeys[1] = nullptr;
   f->scan_tmp2 = f->sort_tmp = nullptr;
+}
+
+int render_phase2(msgs_frame* f, float* rgb_out) {
+  Phase2Bufs b;
+  void* tmp = nullptr;
+  int rc = phase2_alloc(f, b, &tmp, f->st);
+  if (rc != MSGS_OK) return rc;
+  phase2_launch(f, rgb_out, b);
+  release_temporaries(f, tmp, f->st);
   return MSGS_OK;
 }
 
@@ -335,6 +349,21 @@ void msgs_default_opts(msgs_render_opts* o) {
   o->profile = 0;
   o->no_prefilter = 0;
   o->instance_capacity = 0;
+}
+
+msgs_context::~msgs_context() {
+  // the fork streams' work has completed: every multi-view render joined them
+  // back into its caller's stream, and the cache's destructor synchronises
+  (void)hipDeviceSynchronize();
+  for (auto& kv : forks) {
+    msgs::ForkSet* f = kv.second;
+    for (int k = 0; k < msgs::ForkSet::kStreams; ++k) {
+      if (f->s[k]) (void)hipStreamDestroy(f->s[k]);
+      if (f->join[k]) (void)hipEventDestroy(f->join[k]);
+    }
+    if (f->fork) (void)hipEventDestroy(f->fork);
+    delete f;
+  }
 }
 
 int msgs_context_create(int device, size_t pool_bytes, msgs_context** out) {
@@ -364,6 +393,7 @@ int msgs_context_create(int device, size_t pool_bytes, msgs_context** out) {
 
 int msgs_context_destroy(msgs_context* c) {
   if (!c) return fail(MSGS_E_INVALID, "null context");
+  (void)hipSetDevice(c->device);
   delete c;
   return MSGS_OK;
 }
@@ -817,6 +847,39 @@ int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
 // geometry read once), then each view's compaction, depth sort and count scan,
 // one host synchronisation for the instance counts of every exact-mode view,
 // and each view's second phase (the views with the fewest instances first).
+int get_fork_set(msgs_context* c, hipStream_t st, ForkSet** out) {
+  std::lock_guard<std::mutex> g(c->fork_mu);
+  auto it = c->forks.find(st);
+  if (it != c->forks.end()) {
+    *out = it->second;
+    return MSGS_OK;
+  }
+  // stream and event creation are not stream work: made in relaxed capture
+  // mode, so that a first multi-view render under capture can create its set
+  hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+  (void)hipThreadExchangeStreamCaptureMode(&mode);
+  ForkSet* f = new ForkSet();
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < ForkSet::kStreams && e == hipSuccess; ++k)
+    e = hipStreamCreateWithFlags(&f->s[k], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&f->fork, hipEventDisableTiming);
+  for (int k = 0; k < ForkSet::kStreams && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&f->join[k], hipEventDisableTiming);
+  (void)hipThreadExchangeStreamCaptureMode(&mode);
+  if (e != hipSuccess) {
+    for (int k = 0; k < ForkSet::kStreams; ++k) {
+      if (f->s[k]) (void)hipStreamDestroy(f->s[k]);
+      if (f->join[k]) (void)hipEventDestroy(f->join[k]);
+    }
+    if (f->fork) (void)hipEventDestroy(f->fork);
+    delete f;
+    return hip_fail(e, "streams of a multi-view render");
+  }
+  c->forks[st] = f;
+  *out = f;
+  return MSGS_OK;
+}
+
 int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cams,
                           const msgs_render_opts* opts, float* const* rgb_out,
                           msgs_frame** frames_out, int nv, hipStream_t stream,
@@ -882,6 +945,69 @@ int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam
     }
   }
   if (t_waiter) t_waiter->on_admitted();
+  for (msgs_frame* f : fr)
+    if (f->capacity) {
+      f->n_vis = f->n;
+      f->n_inst = f->capacity;
+    }
+  // After the shared projection the views are independent.  With several
+  // views each continues on one of the caller stream's fork streams (view i
+  // on stream i mod kStreams) and the caller's stream waits for all of them
+  // before the instance counts are read and again at the end.  Every buffer
+  // is taken from the cache on the caller's stream before a fork and
+  // returned on it after a join, so the frames belong to the caller's stream
+  // as after a single-view render.
+  int rc = MSGS_OK;
+  ForkSet* fk = nullptr;
+  int nfork = 0;
+  if (nv > 1) {
+    rc = get_fork_set(c, stream, &fk);
+    if (rc != MSGS_OK) {
+      free_all();
+      return rc;
+    }
+    nfork = std::min(nv, ForkSet::kStreams);
+  }
+  bool forked = false;
+  auto fork = [&]() {
+    if (!fk) return;
+    e = hipEventRecord(fk->fork, stream);
+    for (int k = 0; k < nfork && e == hipSuccess; ++k)
+      e = hipStreamWaitEvent(fk->s[k], fk->fork, 0);
+    if (e != hipSuccess && rc == MSGS_OK) rc = hip_fail(e, "fork of a multi-view render");
+    forked = true;
+    for (int i = 0; i < nv; ++i) fr[(size_t)i]->st = fk->s[i % ForkSet::kStreams];
+  };
+  auto join = [&]() {
+    if (!forked) return;
+    hipError_t ej = hipSuccess;
+    for (int k = 0; k < nfork && ej == hipSuccess; ++k) {
+      ej = hipEventRecord(fk->join[k], fk->s[k]);
+      if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, fk->join[k], 0);
+    }
+    if (ej != hipSuccess && rc == MSGS_OK) rc = hip_fail(ej, "join of a multi-view render");
+    forked = false;
+    for (msgs_frame* f : fr) f->st = stream;
+  };
+  std::vector<Phase2Bufs> pb((size_t)nv);
+  std::vector<void*> p2tmp((size_t)nv, nullptr);
+  auto alloc_phase2 = [&]() {
+    for (int i = 0; i < nv && rc == MSGS_OK; ++i)
+      rc = phase2_alloc(fr[(size_t)i], pb[(size_t)i], &p2tmp[(size_t)i], stream);
+  };
+  auto fail_all = [&]() {
+    join();
+    for (int i = 0; i < nv; ++i)
+      if (p2tmp[(size_t)i]) c->cache.free(c, p2tmp[(size_t)i], stream);
+    free_all();
+    if (frames_out)
+      for (int i = 0; i < nv; ++i) frames_out[i] = nullptr;
+    return rc;
+  };
+  if (!any_exact) {
+    alloc_phase2();
+    if (rc != MSGS_OK) return fail_all();
+  }
   for (msgs_frame* f : fr) phase1_zero(f);
   for (int i0 = 0; i0 < nv; i0 += kMaxViews) {
     ProjViews pv;
@@ -892,9 +1018,10 @@ int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam
     }
     launch_project(s->view, pv, stream);
   }
+  fork();
   for (msgs_frame* f : fr) phase1_tail(f);
-  int rc = MSGS_OK;
   if (any_exact) {
+    join();
     CounterList cl;
     cl.n = nv;
     for (int i = 0; i < nv; ++i) cl.p[i] = fr[(size_t)i]->ctr;
@@ -903,7 +1030,7 @@ int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam
     e = hipMemcpyAsync(hc.data(), dcounts, hc.size() * sizeof(unsigned long long),
                        hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) rc = hip_fail(e, "instance count readback");
+    if (e != hipSuccess && rc == MSGS_OK) rc = hip_fail(e, "instance count readback");
     for (int i = 0; i < nv && rc == MSGS_OK; ++i) {
       msgs_frame* f = fr[(size_t)i];
       if (f->capacity) continue;
@@ -913,35 +1040,31 @@ int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam
         rc = fail(MSGS_E_CAPACITY, "more than 2^32 tile instances");
     }
     c->cache.free(c, ctmp.base, stream);
+    if (rc == MSGS_OK) alloc_phase2();
+    if (rc != MSGS_OK) return fail_all();
+    fork();
   }
-  for (msgs_frame* f : fr)
-    if (f->capacity) {
-      f->n_vis = f->n;
-      f->n_inst = f->capacity;
-    }
-  // second phases, fewest instances first (the views are independent)
+  if (rc != MSGS_OK) return fail_all();
+  // second phases, fewest instances first on each stream
   std::vector<int> ord((size_t)nv);
   for (int i = 0; i < nv; ++i) ord[(size_t)i] = i;
   std::stable_sort(ord.begin(), ord.end(),
                    [&](int a, int b) { return fr[(size_t)a]->n_inst < fr[(size_t)b]->n_inst; });
   for (int i : ord) {
-    if (rc != MSGS_OK) break;
-    rc = render_phase2(fr[(size_t)i], rgb_out[i]);
-    if (rc == MSGS_OK && done_ev) {
-      e = hipEventRecord(done_ev[i], stream);
-      if (e != hipSuccess) rc = hip_fail(e, "hipEventRecord");
+    phase2_launch(fr[(size_t)i], rgb_out[i], pb[(size_t)i]);
+    if (done_ev) {
+      e = hipEventRecord(done_ev[i], fr[(size_t)i]->st);
+      if (e != hipSuccess && rc == MSGS_OK) rc = hip_fail(e, "hipEventRecord");
     }
   }
+  join();
+  for (int i = 0; i < nv; ++i) release_temporaries(fr[(size_t)i], p2tmp[(size_t)i], stream);
+  std::fill(p2tmp.begin(), p2tmp.end(), nullptr);
   if (rc == MSGS_OK) {
     e = hipGetLastError();
     if (e != hipSuccess) rc = hip_fail(e, "kernel launch");
   }
-  if (rc != MSGS_OK) {
-    free_all();
-    if (frames_out)
-      for (int i = 0; i < nv; ++i) frames_out[i] = nullptr;
-    return rc;
-  }
+  if (rc != MSGS_OK) return fail_all();
   for (int i = 0; i < nv; ++i) {
     if (frames_out) {
       frames_out[i] = fr[(size_t)i];

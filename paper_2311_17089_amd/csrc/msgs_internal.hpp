@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -52,11 +54,27 @@ struct Carve {
 };
 }  // namespace msgs
 
+namespace msgs {
+// Streams that a multi-view render forks its views onto, with the events that
+// order them after the caller's stream and the caller's stream after them.
+// One set per caller stream (callers on different streams, e.g. the server's
+// slots, never share one), created on first use and kept with the context.
+struct ForkSet {
+  static constexpr int kStreams = 4;
+  hipStream_t s[kStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kStreams] = {};
+};
+}  // namespace msgs
+
 struct msgs_context {
   int device = 0;
   size_t budget = 0;                 // 0 = unlimited
   std::atomic<size_t> in_use{0};     // bytes held by scenes and frames
   msgs::DeviceCache cache;
+  std::mutex fork_mu;
+  std::unordered_map<hipStream_t, msgs::ForkSet*> forks;
+  ~msgs_context();
 };
 
 struct msgs_scene {
@@ -133,6 +151,8 @@ int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
                     const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
                     hipStream_t stream);
 constexpr int kMaxViewsPerCall = 64;
+// The fork set of caller stream st (created on first use).
+int get_fork_set(msgs_context* c, hipStream_t st, ForkSet** out);
 // done_ev (nullable): nv events, event i recorded after view i's last kernel
 int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cams,
                           const msgs_render_opts* opts, float* const* rgb_out,
@@ -160,6 +180,8 @@ void phase1_tail(msgs_frame* f);
 void phase2_layout(msgs_frame* f, Carve& keep, Carve& tmp, Phase2Bufs& b);
 void phase2_launch(msgs_frame* f, float* rgb_out, const Phase2Bufs& b);
 int render_phase1(msgs_frame* f);
+int phase2_alloc(msgs_frame* f, Phase2Bufs& b, void** tmp_block, hipStream_t st);
+void release_temporaries(msgs_frame* f, void* phase2_tmp, hipStream_t st);
 int render_phase2(msgs_frame* f, float* rgb_out);
 // Looks up this device's address of the no-allocation scratch array (the
 // device must be current); once per device, at context creation.
