@@ -210,8 +210,11 @@ int msgs_render(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
  * or of a multi-scale training step, Sec. 4.1 on multi-scale training and
  * selective rendering).  The projection, coverage, selection and range update
  * of up to 8 views run in one pass over the scene that reads each Gaussian's
- * geometry once; each view's binning, sorts and compositing follow on
- * `stream`.  Results (images, frames, statistics, and the scene's s_max/s_min
+ * geometry once; each view's binning, sorts and compositing follow on one
+ * of four streams of the library's own that `stream` forks to after the
+ * projection and joins back from before the call returns, so that views
+ * overlap on the device.  The frames belong to `stream` (as after msgs_render
+ * on it).  Results (images, frames, statistics, and the scene's s_max/s_min
  * when views update ranges) are bit-identical to msgs_render called on the
  * views in order.  Views in exact mode (instance_capacity = 0) share one host
  * synchronisation; with every view in fixed-capacity mode there is none.
@@ -272,14 +275,17 @@ int msgs_render_backward(msgs_context* ctx, const msgs_frame* frame, const float
  * per-view adjoints).  Equivalent to msgs_render_backward on frames[0] with
  * out->accumulate as given, then on frames[1..nviews-1] with accumulate = 1,
  * with bit-identical results: the views' contributions are added in view
- * order in fp32.  The per-view compositing adjoints run one after another;
- * the chain rule then reads each Gaussian's parameters and writes its
- * gradients once for up to eight views (more views take further passes).
+ * order in fp32.  The per-view compositing adjoints and partial sums run on
+ * four streams of the library's own (view i on stream i mod 4) that `stream`
+ * forks to and joins back from; the chain rule then runs on `stream`, reading
+ * each Gaussian's parameters and writing its gradients once for up to eight
+ * views (more views take further passes).
  *   frames   host array of nviews frames of the same scene and context
  *   dL_drgb  host array of nviews device pointers, [H_d][W_d][3] fp32 each
  *   nviews   >= 1 (else MSGS_E_INVALID)
- * Temporary device memory: 48 bytes per Gaussian per view, 4 per Gaussian,
- * and 36 bytes plus one bit per tile instance of the largest frame.  Stream
+ * Temporary device memory: 48 bytes per Gaussian per view, and for each of
+ * the min(nviews, 4) streams 4 bytes per Gaussian and 36 bytes plus one bit
+ * per tile instance of the largest frame that stream takes.  Stream
  * order as for msgs_render_backward, for every frame. */
 int msgs_render_backward_views(msgs_context* ctx, const msgs_frame* const* frames,
                                const float* const* dL_drgb, int nviews, const msgs_grads* out,

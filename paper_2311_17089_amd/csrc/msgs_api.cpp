@@ -1175,26 +1175,51 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
-  float* partial = nullptr;
-  uint32_t* wmask = nullptr;
+  // with several views the per-view work (adjoint compositing, partial sums)
+  // runs on the caller stream's fork streams, view i on stream i mod
+  // kStreams, each stream with its own partials; the chain rule then runs on
+  // the caller's stream after it has joined them
+  ForkSet* fk = nullptr;
+  int nfork = 1;
+  if (nviews > 1) {
+    int rc0 = get_fork_set(c, st, &fk);
+    if (rc0 != MSGS_OK) return rc0;
+    nfork = std::min(nviews, ForkSet::kStreams);
+  }
+  float* partial[ForkSet::kStreams] = {};
+  uint32_t* wmask[ForkSet::kStreams] = {};
+  uint32_t* big[ForkSet::kStreams] = {};
+  uint32_t* nbig[ForkSet::kStreams] = {};
   float* gsum = nullptr;
-  uint32_t* big = nullptr;
-  uint32_t* nbig = nullptr;
   Carve tmp;
-  tmp.add((void**)&partial, (size_t)36 * (size_t)max_inst);
-  tmp.add((void**)&wmask, (size_t)4 * (size_t)((max_inst + 31) / 32));
   tmp.add((void**)&gsum, (size_t)48 * (size_t)n * (size_t)nviews);
-  tmp.add((void**)&big, (size_t)4 * (size_t)n);
-  tmp.add((void**)&nbig, 4);
+  for (int k = 0; k < nfork; ++k) {
+    int64_t mi = 0;
+    for (int i = k; i < nviews; i += nfork) mi = std::max<int64_t>(mi, frames[i]->n_inst);
+    tmp.add((void**)&partial[k], (size_t)36 * (size_t)mi);
+    tmp.add((void**)&wmask[k], (size_t)4 * (size_t)((mi + 31) / 32));
+    tmp.add((void**)&big[k], (size_t)4 * (size_t)n);
+    tmp.add((void**)&nbig[k], 4);
+  }
   for (int i = 0; i < nviews; ++i) {
     int rc0 = frame_order_before(const_cast<msgs_frame*>(frames[i]), st);
     if (rc0 != MSGS_OK) return rc0;
   }
   int rc = tmp.alloc(c, st);
   if (rc != MSGS_OK) return rc;
+  if (fk) {
+    e = hipEventRecord(fk->fork, st);
+    for (int k = 0; k < nfork && e == hipSuccess; ++k) e = hipStreamWaitEvent(fk->s[k], fk->fork, 0);
+    if (e != hipSuccess) {
+      c->cache.free(c, tmp.base, st);
+      return hip_fail(e, "fork of a multi-view backward");
+    }
+  }
   // per view: adjoint compositing and the per-Gaussian partial sums
   for (int i = 0; i < nviews; ++i) {
     const msgs_frame* f = frames[i];
+    const int k = i % nfork;
+    hipStream_t sv = fk ? fk->s[k] : st;
     BwdArgs a{};
     a.s = f->scene->view;
     a.v = f->v;
@@ -1218,14 +1243,21 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
     a.n_last = f->n_last;
     a.dL_drgb = dL_drgb[i];
     a.n_inst = f->n_inst;
-    a.partial = partial;
-    a.wmask = wmask;
+    a.partial = partial[k];
+    a.wmask = wmask[k];
     a.gsum = gsum + (size_t)12 * (size_t)n * (size_t)i;
-    a.big = big;
-    a.nbig = nbig;
-    launch_backward_zero(a, st);
-    launch_backward_blend(a, st);
-    launch_backward_segsum(a, st);
+    a.big = big[k];
+    a.nbig = nbig[k];
+    launch_backward_zero(a, sv);
+    launch_backward_blend(a, sv);
+    launch_backward_segsum(a, sv);
+  }
+  if (fk) {
+    for (int k = 0; k < nfork && e == hipSuccess; ++k) {
+      e = hipEventRecord(fk->join[k], fk->s[k]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, fk->join[k], 0);
+    }
+    if (e != hipSuccess) rc = hip_fail(e, "join of a multi-view backward");
   }
   // chain rule, kChainViews views per pass; later passes add
   for (int i0 = 0; i0 < nviews; i0 += kChainViews) {
