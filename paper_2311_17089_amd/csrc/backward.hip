@@ -489,40 +489,71 @@ __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
   }
 }
 
-// Chain rule of one Gaussian under one view, from its nine summed partials G
-// (dL/du, dL/dA, dL/dopacity, dL/dcolour) back to the parameters.  Each
-// result x of output slot i goes to emit(i, x); the slots are means 0..2,
-// scales 3..5, quats 6..9, opacity 10 and the SH coefficients (j*3 + c) from
-// 11.  geo_shape and geo_view of this view must have filled g.
+// Unit view direction of a Gaussian centre (mu - C) / |mu - C| and the norm.
+__device__ __forceinline__ void view_dir(const ViewParams& v, float mu0, float mu1, float mu2,
+                                         float& x, float& y, float& z, float& dn) {
+  const float dv0 = mu0 - v.C[0], dv1 = mu1 - v.C[1], dv2 = mu2 - v.C[2];
+  dn = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
+  x = dv0 / dn;
+  y = dv1 / dn;
+  z = dv2 / dn;
+}
+
+// The SH-coefficient slots of the chain rule (slot 11 + j*3 + c gets
+// Y_j gc_c), given gc = dL/dcolour with the clamp of the forward's colour
+// applied (what chain_view leaves in gc).
 template <int D, class Emit>
+__device__ __forceinline__ void chain_sh(const ViewParams& v, float mu0, float mu1, float mu2,
+                                         const float* gc, Emit&& emit) {
+  constexpr int K = (D + 1) * (D + 1);
+  float x, y, z, dn;
+  view_dir(v, mu0, mu1, mu2, x, y, z, dn);
+  float Y[16];
+  sh_eval(D, x, y, z, Y);
+#pragma unroll
+  for (int j = 0; j < K; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) emit(11 + j * 3 + c, Y[j] * gc[c]);
+}
+
+// Chain rule of one Gaussian under one view, from its nine summed partials G
+// (dL/du, dL/dA, dL/dopacity, dL/dcolour) back to the parameters, with f its
+// SH coefficients (f[j*3 + c]).  Each result x of output slot i goes to
+// emit(i, x); the slots are means 0..2, scales 3..5, quats 6..9, opacity 10
+// and, when SH is true, the SH coefficients (j*3 + c) from 11 (else chain_sh
+// gives them from gc).  geo_shape and geo_view of this view must have filled
+// g.  gc receives dL/dcolour after the colour clamp.
+template <int D, bool SH, class Emit>
 __device__ __forceinline__ void chain_view(const ViewParams& v, const Geo& g, const float* G,
                                            float mu0, float mu1, float mu2, const float* f,
-                                           Emit&& emit) {
+                                           float* gc, Emit&& emit) {
   constexpr int K = (D + 1) * (D + 1);
-  const float gux = G[0], guy = G[1], gA11 = G[2], gA12 = G[3], gA22 = G[4];
   emit(10, G[5]);
   // ---- colour -> SH coefficients and view direction
-  float dv0 = mu0 - v.C[0], dv1 = mu1 - v.C[1], dv2 = mu2 - v.C[2];
-  const float dn = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
-  const float x = dv0 / dn, y = dv1 / dn, z = dv2 / dn;
-  float Y[16], Yx[16], Yy[16], Yz[16];
+  float x, y, z, dn;
+  view_dir(v, mu0, mu1, mu2, x, y, z, dn);
+  float Y[16];
   sh_eval(D, x, y, z, Y);
-  sh_grad(D, x, y, z, Yx, Yy, Yz);
-  float gdx = 0.0f, gdy = 0.0f, gdz = 0.0f;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     float acc = 0.5f;
 #pragma unroll
     for (int j = 0; j < K; ++j) acc = acc + Y[j] * f[j * 3 + c];
-    const float gc = acc < 0.0f ? 0.0f : G[6 + c];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      emit(11 + j * 3 + c, Y[j] * gc);
-      gdx += gc * f[j * 3 + c] * Yx[j];
-      gdy += gc * f[j * 3 + c] * Yy[j];
-      gdz += gc * f[j * 3 + c] * Yz[j];
-    }
+    gc[c] = acc < 0.0f ? 0.0f : G[6 + c];
   }
+  if (SH) {
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) emit(11 + j * 3 + c, Y[j] * gc[c]);
+  }
+  // dL/d(direction) = sum_j (sum_c gc_c f_jc) dY_j/d(direction)
+  float h[16];
+#pragma unroll
+  for (int j = 0; j < K; ++j) h[j] = (gc[0] * f[j * 3] + gc[1] * f[j * 3 + 1]) + gc[2] * f[j * 3 + 2];
+  float gdx, gdy, gdz;
+  sh_grad_dot(D, x, y, z, h, gdx, gdy, gdz);
+  const float gux = G[0], guy = G[1], gA11 = G[2], gA12 = G[3], gA22 = G[4];
   // unit direction d = v / |v|: dL/dv = (g - d (d . g)) / |v|
   const float dg = x * gdx + y * gdy + z * gdz;
   float gm0 = (gdx - x * dg) / dn, gm1 = (gdy - y * dg) / dn, gm2 = (gdz - z * dg) / dn;
@@ -622,59 +653,70 @@ __device__ __forceinline__ void load9(const float* gsum, int64_t k, float* G) {
   G[8] = c.x;
 }
 
-// Address of output slot i (see chain_view) of Gaussian k in the planar arrays.
-__device__ __forceinline__ float* slot_ptr(const GradPlanes& p, int64_t n, int64_t k, int i) {
-  if (i < 3) return p.means + i * n + k;
-  if (i < 6) return p.scales + (i - 3) * n + k;
-  if (i < 10) return p.quats + (i - 6) * n + k;
-  if (i == 10) return p.opacity + k;
-  return p.sh + (int64_t)(i - 11) * n + k;
+// Output slot i (see chain_view) of the Gaussian at byte offset koff in the
+// planar arrays.
+__device__ __forceinline__ float& slot_at(const GradPlanes& p, int64_t n, uint32_t koff, int i) {
+  if (i < 3) return plane_at(p.means, n, i, koff);
+  if (i < 6) return plane_at(p.scales, n, i - 3, koff);
+  if (i < 10) return plane_at(p.quats, n, i - 6, koff);
+  if (i == 10) return plane_at(p.opacity, n, 0, koff);
+  return plane_at(p.sh, n, i - 11, koff);
 }
 
+// The SH coefficients of the Gaussian at byte offset koff, f[j*3 + c], all
+// loads issued together.
 template <int D>
-__device__ __forceinline__ void load_sh(const SceneView& s, int64_t k, float* f) {
+__device__ __forceinline__ void load_sh(const SceneView& s, uint32_t koff, float* f) {
   constexpr int K = (D + 1) * (D + 1);
 #pragma unroll
-  for (int j = 0; j < K * 3; ++j) f[j] = s.sh[(int64_t)j * s.n + k];
+  for (int j = 0; j < K * 3; ++j) f[j] = plane_at(s.sh, s.n, j, koff);
 }
 
 // One view (SH degree D as a template parameter so that the coefficient loads
 // are issued together).  ACC: add into the gradient planes instead of writing
-// them; Gaussians that do not contribute are then not touched at all.
+// them; Gaussians that do not contribute are then not touched at all.  The
+// writing form fits 128 registers, four waves per SIMD.
 template <int D, bool ACC>
-__global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v, const uint32_t* count,
-                                                  const float* gsum, GradPlanes p) {
+__global__ __launch_bounds__(kBlock, ACC ? 1 : 4) void k_chain(SceneView s, ViewParams v,
+                                                               const uint32_t* count,
+                                                               const float* gsum, GradPlanes p) {
   const int64_t n = s.n;
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
   constexpr int K = (D + 1) * (D + 1);
   Geo g;
   bool live = count[k] > 0 && project_geo(s, v, k, g);
+  const uint32_t koff = plane_off(k);
   if (!live) {
     if (ACC) return;
 #pragma unroll
-    for (int i = 0; i < 11 + K * 3; ++i) *slot_ptr(p, n, k, i) = 0.0f;
+    for (int i = 0; i < 11 + K * 3; ++i) slot_at(p, n, koff, i) = 0.0f;
     return;
   }
-  float G[kNP], f[K * 3];
+  float G[kNP], f[K * 3], gc[3];
   load9(gsum, k, G);
-  load_sh<D>(s, k, f);
+  load_sh<D>(s, koff, f);
   const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
-  chain_view<D>(v, g, G, mu0, mu1, mu2, f, [&](int i, float x) {
-    float* q = slot_ptr(p, n, k, i);
+  chain_view<D, true>(v, g, G, mu0, mu1, mu2, f, gc, [&](int i, float x) {
+    float& q = slot_at(p, n, koff, i);
     if (ACC)
-      *q += x;
+      q += x;
     else
-      *q = x;
+      q = x;
   });
 }
 
 // Several views in one pass: the parameters of a Gaussian are read and its
 // gradients written once, the views' contributions added in view order (the
 // same fp32 additions, in the same order, as one k_chain per view with the
-// first writing and the rest adding).
+// first writing and the rest adding).  Two passes over the views: the
+// geometry and opacity slots (each view's clamped dL/dcolour kept in LDS),
+// then the SH-coefficient slots from those, so that only one group of
+// accumulators is held at a time.  The next view's partial sums are loaded
+// while one view is worked.
 template <int D, bool ACC>
 __global__ __launch_bounds__(kBlock) void k_chain_views(SceneView s, ChainViews cv, GradPlanes p) {
+  __shared__ float sgc[kChainViews][3][kBlock];
   const int64_t n = s.n;
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
@@ -684,27 +726,62 @@ __global__ __launch_bounds__(kBlock) void k_chain_views(SceneView s, ChainViews 
   for (int i = 0; i < cv.nv; ++i) live |= (cv.w[i].count[k] > 0 ? 1u : 0u) << i;
   if (!live) {
     if (ACC) return;
+    const uint32_t koff = plane_off(k);
 #pragma unroll
-    for (int i = 0; i < NO; ++i) *slot_ptr(p, n, k, i) = 0.0f;
+    for (int i = 0; i < NO; ++i) slot_at(p, n, koff, i) = 0.0f;
     return;
   }
   Geo g;
   geo_shape(s, k, g);
-  float f[K * 3];
-  load_sh<D>(s, k, f);
   const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
-  float o[NO];
+  uint32_t front = 0;  // bit i: view i contributes
+  {
+    const uint32_t koff = plane_off(k);
+    float o[11], f[K * 3];
 #pragma unroll
-  for (int i = 0; i < NO; ++i) o[i] = ACC ? *slot_ptr(p, n, k, i) : 0.0f;
-  for (int i = 0; i < cv.nv; ++i) {
-    if (!((live >> i) & 1u)) continue;
-    if (!geo_view(cv.w[i].v, mu0, mu1, mu2, g)) continue;
-    float G[kNP];
-    load9(cv.w[i].gsum, k, G);
-    chain_view<D>(cv.w[i].v, g, G, mu0, mu1, mu2, f, [&](int j, float x) { o[j] = o[j] + x; });
+    for (int i = 0; i < 11; ++i) o[i] = ACC ? slot_at(p, n, koff, i) : 0.0f;
+    load_sh<D>(s, koff, f);
+    int i = __builtin_ctz(live);
+    float Gn[kNP];
+    load9(cv.w[i].gsum, k, Gn);
+    for (;;) {
+      float G[kNP];
+#pragma unroll
+      for (int q = 0; q < kNP; ++q) G[q] = Gn[q];
+      const uint32_t rest = live & ~((2u << i) - 1u);
+      const int i2 = rest ? __builtin_ctz(rest) : -1;
+      if (i2 >= 0) load9(cv.w[i2].gsum, k, Gn);
+      if (geo_view(cv.w[i].v, mu0, mu1, mu2, g)) {
+        front |= 1u << i;
+        float gc[3];
+        chain_view<D, false>(cv.w[i].v, g, G, mu0, mu1, mu2, f, gc,
+                             [&](int j, float x) { o[j] = o[j] + x; });
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sgc[i][c][threadIdx.x] = gc[c];
+      }
+      if (i2 < 0) break;
+      i = i2;
+    }
+    const uint32_t koff2 = plane_off(k);
+#pragma unroll
+    for (int q = 0; q < 11; ++q) slot_at(p, n, koff2, q) = o[q];
   }
+  {
+    float o[K * 3];
+    {
+      const uint32_t koff = plane_off(k);
 #pragma unroll
-  for (int i = 0; i < NO; ++i) *slot_ptr(p, n, k, i) = o[i];
+      for (int i = 0; i < K * 3; ++i) o[i] = ACC ? slot_at(p, n, koff, 11 + i) : 0.0f;
+    }
+    for (int i = 0; i < cv.nv; ++i) {
+      if (!((front >> i) & 1u)) continue;
+      const float gc[3] = {sgc[i][0][threadIdx.x], sgc[i][1][threadIdx.x], sgc[i][2][threadIdx.x]};
+      chain_sh<D>(cv.w[i].v, mu0, mu1, mu2, gc, [&](int j, float x) { o[j - 11] = o[j - 11] + x; });
+    }
+    const uint32_t koff = plane_off(k);
+#pragma unroll
+    for (int i = 0; i < K * 3; ++i) slot_at(p, n, koff, 11 + i) = o[i];
+  }
 }
 
 static inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }

@@ -147,8 +147,9 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ProjViews pv) {
             d2 = d2 / dn;
             constexpr int K = (D + 1) * (D + 1);
             float f[K * 3];
+            const uint32_t koff = plane_off(k);
 #pragma unroll
-            for (int j = 0; j < K * 3; ++j) f[j] = s.sh[(int64_t)j * n + k];
+            for (int j = 0; j < K * 3; ++j) f[j] = plane_at(s.sh, n, j, koff);
             float Y[16];
             sh_eval(D, d0, d1, d2, Y);
             float col[3];

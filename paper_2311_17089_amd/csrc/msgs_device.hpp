@@ -49,6 +49,28 @@ struct ViewParams {
   int prefilter;         // apply the conservative pre-splat coverage bound
 };
 
+// Element of plane j of a planar array (planes of n floats) at byte offset
+// koff (4 k for element k, below 4 GiB): the plane's base is the same for
+// the whole wave and the offset one 32-bit register, so a thread that reads
+// many planes holds one offset instead of a 64-bit address per plane.
+__device__ __forceinline__ const float& plane_at(const float* base, int64_t n, int j,
+                                                uint32_t koff) {
+  return *(const float*)((const char*)(base + (int64_t)j * n) + koff);
+}
+__device__ __forceinline__ float& plane_at(float* base, int64_t n, int j, uint32_t koff) {
+  return *(float*)((char*)(base + (int64_t)j * n) + koff);
+}
+// 4 k as such an offset, made opaque to the compiler by an empty asm statement
+// that claims to change it: taken right before a group of plane accesses, it
+// keeps the compiler from hoisting one 64-bit address per plane out of a loop
+// (or ahead of the code that needs them), which cost about 100 registers in
+// the multi-view kernels.
+__device__ __forceinline__ uint32_t plane_off(int64_t k) {
+  uint32_t o = (uint32_t)k * 4u;
+  asm volatile("" : "+v"(o));
+  return o;
+}
+
 // Projected record of a drawable Gaussian, three float4 per Gaussian index:
 //   r0 = (u_x, u_y, A11, A12)
 //   r1 = (A22, sigma, -(lnq + 2^-8), red)
@@ -149,30 +171,30 @@ __device__ __forceinline__ void sh_eval(int D, float x, float y, float z, float*
   Y[15] = kY3a * (x * (xx - 3.0f * yy));
 }
 
-// Gradient of each basis function w.r.t. (x, y, z), treating the three
-// coordinates as independent (the caller projects onto the sphere's tangent).
-__device__ __forceinline__ void sh_grad(int D, float x, float y, float z, float* gx, float* gy,
-                                        float* gz) {
-  gx[0] = gy[0] = gz[0] = 0.0f;
+// Sum over the basis of h[j] times the gradient of Y_j w.r.t. (x, y, z), the
+// three coordinates treated as independent (the caller projects onto the
+// sphere's tangent).  The gradients are not formed one by one, and the terms
+// of a derivative that is identically zero are left out.
+__device__ __forceinline__ void sh_grad_dot(int D, float x, float y, float z, const float* h,
+                                            float& gx, float& gy, float& gz) {
+  gx = gy = gz = 0.0f;
   if (D < 1) return;
-  gx[1] = 0.0f; gy[1] = kY1;  gz[1] = 0.0f;
-  gx[2] = 0.0f; gy[2] = 0.0f; gz[2] = kY1;
-  gx[3] = kY1;  gy[3] = 0.0f; gz[3] = 0.0f;
+  gx = kY1 * h[3];
+  gy = kY1 * h[1];
+  gz = kY1 * h[2];
   if (D < 2) return;
-  gx[4] = kY2a * y;  gy[4] = kY2a * x;  gz[4] = 0.0f;
-  gx[5] = 0.0f;      gy[5] = kY2a * z;  gz[5] = kY2a * y;
-  gx[6] = 0.0f;      gy[6] = 0.0f;      gz[6] = kY2b * (6.0f * z);
-  gx[7] = kY2a * z;  gy[7] = 0.0f;      gz[7] = kY2a * x;
-  gx[8] = kY2c * (2.0f * x); gy[8] = kY2c * (-2.0f * y); gz[8] = 0.0f;
+  gx = gx + kY2a * (y * h[4] + z * h[7]) + kY2c * (2.0f * x) * h[8];
+  gy = gy + kY2a * (x * h[4] + z * h[5]) - kY2c * (2.0f * y) * h[8];
+  gz = gz + kY2a * (y * h[5] + x * h[7]) + kY2b * (6.0f * z) * h[6];
   if (D < 3) return;
-  float xx = x * x, yy = y * y, zz = z * z;
-  gx[9] = kY3a * (6.0f * x * y);          gy[9] = kY3a * (3.0f * xx - 3.0f * yy);  gz[9] = 0.0f;
-  gx[10] = kY3b * (y * z);                gy[10] = kY3b * (x * z);                gz[10] = kY3b * (x * y);
-  gx[11] = 0.0f;                          gy[11] = kY3c * (5.0f * zz - 1.0f);     gz[11] = kY3c * (10.0f * y * z);
-  gx[12] = 0.0f;                          gy[12] = 0.0f;                          gz[12] = kY3d * (15.0f * zz - 3.0f);
-  gx[13] = kY3c * (5.0f * zz - 1.0f);     gy[13] = 0.0f;                          gz[13] = kY3c * (10.0f * x * z);
-  gx[14] = kY3e * (2.0f * x * z);         gy[14] = kY3e * (-2.0f * y * z);        gz[14] = kY3e * (xx - yy);
-  gx[15] = kY3a * (3.0f * xx - 3.0f * yy); gy[15] = kY3a * (-6.0f * x * y);       gz[15] = 0.0f;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float z5 = 5.0f * zz - 1.0f;
+  gx = gx + kY3a * ((6.0f * x * y) * h[9] + (3.0f * xx - 3.0f * yy) * h[15]) +
+       kY3b * (y * z) * h[10] + kY3c * z5 * h[13] + kY3e * (2.0f * x * z) * h[14];
+  gy = gy + kY3a * ((3.0f * xx - 3.0f * yy) * h[9] - (6.0f * x * y) * h[15]) +
+       kY3b * (x * z) * h[10] + kY3c * z5 * h[11] - kY3e * (2.0f * y * z) * h[14];
+  gz = gz + kY3b * (x * y) * h[10] + kY3c * ((10.0f * y * z) * h[11] + (10.0f * x * z) * h[13]) +
+       kY3d * (15.0f * zz - 3.0f) * h[12] + kY3e * (xx - yy) * h[14];
 }
 
 // ------------------------------------------------------------------ projection
