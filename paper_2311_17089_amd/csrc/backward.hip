@@ -674,10 +674,9 @@ __device__ __forceinline__ void load_sh(const SceneView& s, uint32_t koff, float
 
 // One view (SH degree D as a template parameter so that the coefficient loads
 // are issued together).  ACC: add into the gradient planes instead of writing
-// them; Gaussians that do not contribute are then not touched at all.  The
-// writing form fits 128 registers, four waves per SIMD.
+// them; Gaussians that do not contribute are then not touched at all.
 template <int D, bool ACC>
-__global__ __launch_bounds__(kBlock, ACC ? 1 : 4) void k_chain(SceneView s, ViewParams v,
+__global__ __launch_bounds__(kBlock) void k_chain(SceneView s, ViewParams v,
                                                                const uint32_t* count,
                                                                const float* gsum, GradPlanes p) {
   const int64_t n = s.n;
@@ -686,7 +685,7 @@ __global__ __launch_bounds__(kBlock, ACC ? 1 : 4) void k_chain(SceneView s, View
   constexpr int K = (D + 1) * (D + 1);
   Geo g;
   bool live = count[k] > 0 && project_geo(s, v, k, g);
-  const uint32_t koff = plane_off(k);
+  const uint32_t koff = (uint32_t)k * 4u;
   if (!live) {
     if (ACC) return;
 #pragma unroll
@@ -726,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_views(SceneView s, ChainViews 
   for (int i = 0; i < cv.nv; ++i) live |= (cv.w[i].count[k] > 0 ? 1u : 0u) << i;
   if (!live) {
     if (ACC) return;
-    const uint32_t koff = plane_off(k);
+    const uint32_t koff = (uint32_t)k * 4u;
 #pragma unroll
     for (int i = 0; i < NO; ++i) slot_at(p, n, koff, i) = 0.0f;
     return;
@@ -736,7 +735,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_views(SceneView s, ChainViews 
   const float mu0 = s.means[k], mu1 = s.means[n + k], mu2 = s.means[2 * n + k];
   uint32_t front = 0;  // bit i: view i contributes
   {
-    const uint32_t koff = plane_off(k);
+    const uint32_t koff = (uint32_t)k * 4u;
     float o[11], f[K * 3];
 #pragma unroll
     for (int i = 0; i < 11; ++i) o[i] = ACC ? slot_at(p, n, koff, i) : 0.0f;
@@ -762,14 +761,13 @@ __global__ __launch_bounds__(kBlock) void k_chain_views(SceneView s, ChainViews 
       if (i2 < 0) break;
       i = i2;
     }
-    const uint32_t koff2 = plane_off(k);
 #pragma unroll
-    for (int q = 0; q < 11; ++q) slot_at(p, n, koff2, q) = o[q];
+    for (int q = 0; q < 11; ++q) slot_at(p, n, koff, q) = o[q];
   }
   {
     float o[K * 3];
     {
-      const uint32_t koff = plane_off(k);
+      const uint32_t koff = (uint32_t)k * 4u;
 #pragma unroll
       for (int i = 0; i < K * 3; ++i) o[i] = ACC ? slot_at(p, n, koff, 11 + i) : 0.0f;
     }
@@ -778,7 +776,7 @@ __global__ __launch_bounds__(kBlock) void k_chain_views(SceneView s, ChainViews 
       const float gc[3] = {sgc[i][0][threadIdx.x], sgc[i][1][threadIdx.x], sgc[i][2][threadIdx.x]};
       chain_sh<D>(cv.w[i].v, mu0, mu1, mu2, gc, [&](int j, float x) { o[j - 11] = o[j - 11] + x; });
     }
-    const uint32_t koff = plane_off(k);
+    const uint32_t koff = (uint32_t)k * 4u;
 #pragma unroll
     for (int i = 0; i < K * 3; ++i) slot_at(p, n, koff, 11 + i) = o[i];
   }

@@ -61,10 +61,11 @@ __device__ __forceinline__ float& plane_at(float* base, int64_t n, int j, uint32
   return *(float*)((char*)(base + (int64_t)j * n) + koff);
 }
 // 4 k as such an offset, made opaque to the compiler by an empty asm statement
-// that claims to change it: taken right before a group of plane accesses, it
-// keeps the compiler from hoisting one 64-bit address per plane out of a loop
-// (or ahead of the code that needs them), which cost about 100 registers in
-// the multi-view kernels.
+// that claims to change it: taken inside a loop, right before the loop body's
+// plane accesses, it keeps the compiler from hoisting one 64-bit address per
+// plane out of the loop (about 100 registers in the multi-view projection).
+// The statement also orders memory accesses around it, so it is kept out of
+// code without such a loop.
 __device__ __forceinline__ uint32_t plane_off(int64_t k) {
   uint32_t o = (uint32_t)k * 4u;
   asm volatile("" : "+v"(o));
