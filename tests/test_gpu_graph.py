@@ -72,9 +72,14 @@ def test_fixed_capacity_matches_exact_and_reports_overflow():
     dsc.close()
 
 
-@pytest.mark.parametrize("views_backward", [False, True])
-def test_captured_training_step_replays_exactly(views_backward):
-    _say(f"  captured step, multi-view backward {views_backward}")
+@pytest.mark.parametrize("mode", ["per_view", "views_backward", "multi_view"])
+def test_captured_training_step_replays_exactly(mode):
+    # per_view: one render and one backward call per view; views_backward: one
+    # render call per view, one multi-view backward; multi_view: one
+    # multi-view render call (its views run on the library's fork streams
+    # inside the capture) and one multi-view backward
+    _say(f"  captured step, {mode}")
+    views_backward = mode != "per_view"
     ctx = M.Context(0)
     dsc = _scene(ctx)
     views = _views()
@@ -95,7 +100,12 @@ def test_captured_training_step_replays_exactly(views_backward):
             for k in NAMES:
                 grads[k].copy_(zeros[k])
         fs = []
+        if mode == "multi_view":
+            vl = [(cam, {"downscale": d, "capacity": cap}) for (cam, d), cap in zip(views, caps)]
+            _, fs = M.render_views(ctx, dsc, vl, keep_frames=True, outs=outs)
         for (cam, d), dl, cap, o in zip(views, dls, caps, outs):
+            if mode == "multi_view":
+                break
             _, fr = M.render(ctx, dsc, cam, downscale=d, keep_frame=True, capacity=cap, out=o)
             if not views_backward:
                 M.render_backward(ctx, fr, dl, grads=grads, accumulate=True)
