@@ -66,7 +66,8 @@ typedef struct msgs_server msgs_server;
  *   level[n]        level of detail, 0 = finest (creation downscale 4^level)
  *   s_max[n], s_min[n]  stored pixel-coverage range (px); (0, +inf) means
  *                   "never updated"
- * sh_degree D in 0..3; n_levels L in 1..8 with level < L.
+ * n in 0 .. 2^30 - 1 (kernels address a plane's element by a 32-bit byte
+ * offset); sh_degree D in 0..3; n_levels L in 1..8 with level < L.
  * ptrs_on_device: 1 if all pointers are device addresses, 0 if host. */
 typedef struct {
   int64_t n;

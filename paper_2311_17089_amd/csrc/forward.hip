@@ -85,6 +85,15 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ProjViews pv) {
     const float y255 = 255.0f * sig;
     const bool vis = y255 > 1.0f;
     const float lnq = vis ? log_c(y255) : 0.0f;
+    // several views: the SH coefficients are loaded once, before the view
+    // loop (loads inside it let the compiler hoist a 64-bit address per
+    // coefficient plane out of the loop, 96 registers)
+    constexpr int KP = MULTI ? (D + 1) * (D + 1) * 3 : 1;
+    float fpre[KP];
+    if (MULTI && vis) {
+#pragma unroll
+      for (int j = 0; j < KP; ++j) fpre[j] = s.sh[(int64_t)j * n + k];
+    }
     for (int i = 0; i < nv; ++i) {
       const ViewParams& v = pv.v[i];
       const ProjOut& o = pv.o[i];
@@ -147,9 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_project(SceneView s, ProjViews pv) {
             d2 = d2 / dn;
             constexpr int K = (D + 1) * (D + 1);
             float f[K * 3];
-            const uint32_t koff = plane_off(k);
 #pragma unroll
-            for (int j = 0; j < K * 3; ++j) f[j] = plane_at(s.sh, n, j, koff);
+            for (int j = 0; j < K * 3; ++j) f[j] = MULTI ? fpre[j < KP ? j : 0] : s.sh[(int64_t)j * n + k];
             float Y[16];
             sh_eval(D, d0, d1, d2, Y);
             float col[3];

@@ -407,7 +407,7 @@ int msgs_context_bytes_in_use(const msgs_context* c, size_t* out) {
 int msgs_scene_create(msgs_context* c, const msgs_scene_desc* d, int copy, msgs_scene** out) {
   if (!c || !d || !out) return fail(MSGS_E_INVALID, "null argument");
   if (d->n < 0) return fail(MSGS_E_INVALID, "n < 0");
-  if (d->n >= (int64_t)1 << 32) return fail(MSGS_E_INVALID, "n must be < 2^32");
+  if (d->n >= (int64_t)1 << 30) return fail(MSGS_E_INVALID, "n must be < 2^30");
   if (d->sh_degree < 0 || d->sh_degree > 3) return fail(MSGS_E_INVALID, "sh_degree must be 0..3");
   if (d->n_levels < 1 || d->n_levels > 8) return fail(MSGS_E_INVALID, "n_levels must be 1..8");
   const int64_t n = d->n;

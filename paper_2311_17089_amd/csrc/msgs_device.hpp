@@ -60,17 +60,6 @@ __device__ __forceinline__ const float& plane_at(const float* base, int64_t n, i
 __device__ __forceinline__ float& plane_at(float* base, int64_t n, int j, uint32_t koff) {
   return *(float*)((char*)(base + (int64_t)j * n) + koff);
 }
-// 4 k as such an offset, made opaque to the compiler by an empty asm statement
-// that claims to change it: taken inside a loop, right before the loop body's
-// plane accesses, it keeps the compiler from hoisting one 64-bit address per
-// plane out of the loop (about 100 registers in the multi-view projection).
-// The statement also orders memory accesses around it, so it is kept out of
-// code without such a loop.
-__device__ __forceinline__ uint32_t plane_off(int64_t k) {
-  uint32_t o = (uint32_t)k * 4u;
-  asm volatile("" : "+v"(o));
-  return o;
-}
 
 // Projected record of a drawable Gaussian, three float4 per Gaussian index:
 //   r0 = (u_x, u_y, A11, A12)

@@ -248,6 +248,14 @@ def test_invalid_arguments(ctx):
         M.render(ctx, dsc, cam, downscale=64, out=torch.empty(1, 1, 3, device="cuda"))
     assert e.value.code == M.E_INVALID
     dsc.close()
+    # scene sizes: 2^30 Gaussians and more, or a negative count, are rejected
+    # before any pointer is read
+    import ctypes as C
+    for n in (1 << 30, -1):
+        d = M.SceneDesc()
+        d.n, d.sh_degree, d.n_levels, d.ptrs_on_device = n, 0, 1, 1
+        h = C.c_void_p()
+        assert M.lib().msgs_scene_create(ctx.h, C.byref(d), 0, C.byref(h)) == M.E_INVALID
 
 
 def test_prefilter_is_exact(ctx):
