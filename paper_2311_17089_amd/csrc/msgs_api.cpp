@@ -883,7 +883,7 @@ int get_fork_set(msgs_context* c, hipStream_t st, ForkSet** out) {
 int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cams,
                           const msgs_render_opts* opts, float* const* rgb_out,
                           msgs_frame** frames_out, int nv, hipStream_t stream,
-                          hipEvent_t* done_ev) {
+                          hipEvent_t* done_ev, bool fork_views) {
   if (!c || !s || !cams || !opts || !rgb_out) return fail(MSGS_E_INVALID, "null argument");
   if (s->ctx != c) return fail(MSGS_E_INVALID, "scene belongs to another context");
   if (nv < 1 || nv > kMaxViewsPerCall) return fail(MSGS_E_INVALID, "nviews out of range");
@@ -960,7 +960,7 @@ int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam
   int rc = MSGS_OK;
   ForkSet* fk = nullptr;
   int nfork = 0;
-  if (nv > 1) {
+  if (nv > 1 && fork_views) {
     rc = get_fork_set(c, stream, &fk);
     if (rc != MSGS_OK) {
       free_all();
@@ -1084,7 +1084,7 @@ int msgs_render_views(msgs_context* c, msgs_scene* s, const msgs_camera* cams,
                       const msgs_render_opts* opts, float* const* rgb_out,
                       msgs_frame** frames_out, int nviews, void* stream) {
   return render_views_internal(c, s, cams, opts, rgb_out, frames_out, nviews,
-                               (hipStream_t)stream, nullptr);
+                               (hipStream_t)stream, nullptr, true);
 }
 
 int msgs_render_backward(msgs_context* c, const msgs_frame* f, const float* dL_drgb,

@@ -153,11 +153,15 @@ int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
 constexpr int kMaxViewsPerCall = 64;
 // The fork set of caller stream st (created on first use).
 int get_fork_set(msgs_context* c, hipStream_t st, ForkSet** out);
-// done_ev (nullable): nv events, event i recorded after view i's last kernel
+// done_ev (nullable): nv events, event i recorded after view i's last kernel.
+// fork: run the views after the projection on the caller stream's fork
+// streams (false: all on `stream`; the server, whose slots already overlap on
+// their own streams, keeps the streams to one per slot, since streams beyond
+// the device's hardware queues share queues and serialise).
 int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cams,
                           const msgs_render_opts* opts, float* const* rgb_out,
                           msgs_frame** frames_out, int nv, hipStream_t stream,
-                          hipEvent_t* done_ev);
+                          hipEvent_t* done_ev, bool fork);
 extern thread_local std::string t_err;
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);

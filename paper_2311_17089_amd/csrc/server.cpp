@@ -139,7 +139,7 @@ void worker_loop(msgs_server* s, int slot) {
       frames.assign((size_t)nb, nullptr);
       t_waiter = &w;
       rc = render_views_internal(s->ctx, s->scene, cams.data(), opts.data(), rgbs.data(),
-                                 frames.data(), nb, st, evs);
+                                 frames.data(), nb, st, evs, false);
       t_waiter = nullptr;
       if (rc != MSGS_E_NOMEM || nb == 1) break;
       // the batch does not fit: the rest goes back to the head of the queue
