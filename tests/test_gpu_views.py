@@ -148,6 +148,53 @@ def test_views_capacity_mode_and_multi_view_backward(ctx):
     dsc.close()
 
 
+def test_views_mixed_modes_and_backward_on_another_stream(ctx):
+    # one call mixing exact and fixed-capacity views (the capacity views' second
+    # phase waits for the exact views' count readback), rendered on one stream
+    # and differentiated on another, frames released right after: the same
+    # frames, images and gradients as sequential renders on the default stream
+    sc = _scene(95)
+    dsc = M.DeviceScene(ctx, sc)
+    views = _views(195, 6)
+    seq, caps, dls, seq_frames = [], [], [], []
+    for i, (cam, kw) in enumerate(views):
+        img, fr = M.render(ctx, dsc, cam, keep_frame=True, **kw)
+        seq.append(_frame_data(fr, img))
+        caps.append(fr.stats()["n_instances"] + 321 if i % 2 else 0)
+        g = torch.Generator().manual_seed(500 + i)
+        dls.append((torch.randn(img.shape, generator=g) * 1e-2).cuda())
+        seq_frames.append(fr)
+    ref = {k: v.cpu().numpy() for k, v in M.render_backward_views(ctx, seq_frames, dls).items()}
+    for fr in seq_frames:
+        fr.release()
+    mviews = [(cam, dict(kw, capacity=c)) for (cam, kw), c in zip(views, caps)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s1):
+        imgs, frames = M.render_views(ctx, dsc, mviews, keep_frames=True)
+    for i, (img, fr) in enumerate(zip(imgs, frames)):
+        s1.synchronize()
+        got = _frame_data(fr, img)
+        if caps[i]:
+            # a fixed-capacity frame counts the capacity as its instances
+            for key in ("img", "sel", "T", "nc"):
+                np.testing.assert_array_equal(got[key], seq[i][key], err_msg=f"view {i} {key}")
+        else:
+            _same(got, seq[i], f"view {i}")
+    s2.wait_stream(s1)
+    with torch.cuda.stream(s2):
+        grads = M.render_backward_views(ctx, frames, dls)
+    for fr in frames:
+        fr.release()
+    # unrelated work that may take the released blocks
+    with torch.cuda.stream(s1):
+        M.render(ctx, dsc, views[0][0], **views[0][1])
+    torch.cuda.synchronize()
+    for k in ref:
+        np.testing.assert_array_equal(grads[k].cpu().numpy(), ref[k], err_msg=k)
+    dsc.close()
+
+
 def test_views_invalid_arguments(ctx):
     sc = G.make_scene([100], 1, 0, [-3.0])
     dsc = M.DeviceScene(ctx, sc)
