@@ -958,11 +958,16 @@ int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam
   // returned on it after a join, so the frames belong to the caller's stream
   // as after a single-view render.
   int rc = MSGS_OK;
+  auto free_counts = [&]() {
+    if (ctmp.base) c->cache.free(c, ctmp.base, stream);
+    ctmp.base = nullptr;
+  };
   ForkSet* fk = nullptr;
   int nfork = 0;
   if (nv > 1 && fork_views) {
     rc = get_fork_set(c, stream, &fk);
     if (rc != MSGS_OK) {
+      free_counts();
       free_all();
       return rc;
     }
@@ -997,6 +1002,7 @@ int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam
   };
   auto fail_all = [&]() {
     join();
+    free_counts();
     for (int i = 0; i < nv; ++i)
       if (p2tmp[(size_t)i]) c->cache.free(c, p2tmp[(size_t)i], stream);
     free_all();
@@ -1039,7 +1045,7 @@ int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam
       if (hc[2 * (size_t)i + 1] >= (1ull << 32))
         rc = fail(MSGS_E_CAPACITY, "more than 2^32 tile instances");
     }
-    c->cache.free(c, ctmp.base, stream);
+    free_counts();
     if (rc == MSGS_OK) alloc_phase2();
     if (rc != MSGS_OK) return fail_all();
     fork();
