@@ -489,14 +489,21 @@ __global__ __launch_bounds__(kBlock) void k_seg_big(const uint32_t* count,
   }
 }
 
-// Unit view direction of a Gaussian centre (mu - C) / |mu - C| and the norm.
+// The chain rule is not part of the bit-exact contract (its results are
+// gradients, compared within a tolerance): it takes the hardware square root
+// and reciprocal (about 1 ulp each) in place of correctly rounded square
+// roots and divisions, which cost about ten instructions each.
+__device__ __forceinline__ float rcp_hw(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Unit view direction of a Gaussian centre (mu - C) / |mu - C|, the norm and
+// its reciprocal.
 __device__ __forceinline__ void view_dir(const ViewParams& v, float mu0, float mu1, float mu2,
-                                         float& x, float& y, float& z, float& dn) {
+                                         float& x, float& y, float& z, float& idn) {
   const float dv0 = mu0 - v.C[0], dv1 = mu1 - v.C[1], dv2 = mu2 - v.C[2];
-  dn = sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2);
-  x = dv0 / dn;
-  y = dv1 / dn;
-  z = dv2 / dn;
+  idn = rcp_hw(__builtin_amdgcn_sqrtf((dv0 * dv0 + dv1 * dv1) + dv2 * dv2));
+  x = dv0 * idn;
+  y = dv1 * idn;
+  z = dv2 * idn;
 }
 
 // The SH-coefficient slots of the chain rule (slot 11 + j*3 + c gets
@@ -506,8 +513,8 @@ template <int D, class Emit>
 __device__ __forceinline__ void chain_sh(const ViewParams& v, float mu0, float mu1, float mu2,
                                          const float* gc, Emit&& emit) {
   constexpr int K = (D + 1) * (D + 1);
-  float x, y, z, dn;
-  view_dir(v, mu0, mu1, mu2, x, y, z, dn);
+  float x, y, z, idn;
+  view_dir(v, mu0, mu1, mu2, x, y, z, idn);
   float Y[16];
   sh_eval(D, x, y, z, Y);
 #pragma unroll
@@ -530,8 +537,8 @@ __device__ __forceinline__ void chain_view(const ViewParams& v, const Geo& g, co
   constexpr int K = (D + 1) * (D + 1);
   emit(10, G[5]);
   // ---- colour -> SH coefficients and view direction
-  float x, y, z, dn;
-  view_dir(v, mu0, mu1, mu2, x, y, z, dn);
+  float x, y, z, idn;
+  view_dir(v, mu0, mu1, mu2, x, y, z, idn);
   float Y[16];
   sh_eval(D, x, y, z, Y);
 #pragma unroll
@@ -556,11 +563,12 @@ __device__ __forceinline__ void chain_view(const ViewParams& v, const Geo& g, co
   const float gux = G[0], guy = G[1], gA11 = G[2], gA12 = G[3], gA22 = G[4];
   // unit direction d = v / |v|: dL/dv = (g - d (d . g)) / |v|
   const float dg = x * gdx + y * gdy + z * gdz;
-  float gm0 = (gdx - x * dg) / dn, gm1 = (gdy - y * dg) / dn, gm2 = (gdz - z * dg) / dn;
+  float gm0 = (gdx - x * dg) * idn, gm1 = (gdy - y * dg) * idn, gm2 = (gdz - z * dg) * idn;
   // ---- conic A = (V + hI)^-1 -> V
   const float W11 = g.V11 + v.lowpass, W22 = g.V22 + v.lowpass, W12 = g.V12;
   const float det2 = W11 * W22 - W12 * W12;
-  const float A11 = W22 / det2, A12 = -(W12 / det2), A22 = W11 / det2;
+  const float idet = rcp_hw(det2);
+  const float A11 = W22 * idet, A12 = -(W12 * idet), A22 = W11 * idet;
   const float gV11 = -(gA11 * A11 * A11 + gA12 * A11 * A12 + gA22 * A12 * A12);
   const float gV22 = -(gA11 * A12 * A12 + gA12 * A12 * A22 + gA22 * A22 * A22);
   const float gV12 = -(2.0f * gA11 * A11 * A12 + gA12 * (A11 * A22 + A12 * A12) +
@@ -595,7 +603,7 @@ __device__ __forceinline__ void chain_view(const ViewParams& v, const Geo& g, co
   const float gJ11 = gt1[0] * R[3] + gt1[1] * R[4] + gt1[2] * R[5];
   const float gJ12 = gt1[0] * R[6] + gt1[1] * R[7] + gt1[2] * R[8];
   const float px = g.p[0], py = g.p[1], pz = g.p[2];
-  const float iz = 1.0f / pz, iz2 = iz * iz, iz3 = iz2 * iz;
+  const float iz = rcp_hw(pz), iz2 = iz * iz, iz3 = iz2 * iz;
   float gp0 = gJ02 * (-v.fx * iz2) + gux * v.fx * iz;
   float gp1 = gJ12 * (-v.fy * iz2) + guy * v.fy * iz;
   float gp2 = gJ00 * (-v.fx * iz2) + gJ02 * (2.0f * v.fx * px * iz3) + gJ11 * (-v.fy * iz2) +
@@ -630,7 +638,7 @@ __device__ __forceinline__ void chain_view(const ViewParams& v, const Geo& g, co
   const float gz = -4.0f * qz * gQ[0] - 2.0f * w * gQ[1] + 2.0f * qx * gQ[2] + 2.0f * w * gQ[3] -
                    4.0f * qz * gQ[4] + 2.0f * qy * gQ[5] + 2.0f * qx * gQ[6] + 2.0f * qy * gQ[7];
   const float dq = w * gw + qx * gx + qy * gy + qz * gz;
-  const float il = 1.0f / g.qlen;
+  const float il = rcp_hw(g.qlen);
   emit(6, (gw - w * dq) * il);
   emit(7, (gx - qx * dq) * il);
   emit(8, (gy - qy * dq) * il);

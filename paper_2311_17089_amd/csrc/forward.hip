@@ -47,10 +47,14 @@ __device__ __forceinline__ bool prefilter_unselected(const ViewParams& v, int n_
   if (!(pz > 1.001f * v.near_z)) return false;  // depth near the plane: exact path
   const float smn = fminf(fminf(s0, s1), s2);
   const float smd = fmaxf(fminf(s0, s1), fminf(fmaxf(s0, s1), s2));
-  const float xr = px / pz, yr = py / pz;
-  const float flo = fminf(v.fx, v.fy) / pz, fhi = fmaxf(v.fx, v.fy) / pz;
-  const float lo = sqrtf(8.0f * lnq) * flo * smn * 0.999f;
-  const float hi = sqrtf(16.0f * lnq * (1.0f + (xr * xr + yr * yr))) * fhi * smd * 1.001f;
+  // the hardware reciprocal and square root (about 1 ulp each) are far
+  // inside the 1e-3 margins
+  const float iz = __builtin_amdgcn_rcpf(pz);
+  const float xr = px * iz, yr = py * iz;
+  const float flo = fminf(v.fx, v.fy) * iz, fhi = fmaxf(v.fx, v.fy) * iz;
+  const float lo = __builtin_amdgcn_sqrtf(8.0f * lnq) * flo * smn * 0.999f;
+  const float hi =
+      __builtin_amdgcn_sqrtf(16.0f * lnq * (1.0f + (xr * xr + yr * yr))) * fhi * smd * 1.001f;
   const bool g1_fails = l > 0 && lo > 1.5f * smax;
   const bool g2_fails = l < n_levels - 1 && hi < 0.5f * smin && hi < 2.0f;
   return g1_fails || g2_fails;
