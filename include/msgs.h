@@ -214,8 +214,9 @@ int msgs_render(msgs_context* ctx, msgs_scene* scene, const msgs_camera* cam,
  * geometry once; each view's binning, sorts and compositing follow on one
  * of four streams of the library's own that `stream` forks to after the
  * projection and joins back from before the call returns, so that views
- * overlap on the device.  The frames belong to `stream` (as after msgs_render
- * on it).  Results (images, frames, statistics, and the scene's s_max/s_min
+ * overlap on the device (a context keeps such streams for up to 64 caller
+ * streams; calls on further streams run every view on `stream`).  The frames
+ * belong to `stream` (as after msgs_render on it).  Results (images, frames, statistics, and the scene's s_max/s_min
  * when views update ranges) are bit-identical to msgs_render called on the
  * views in order.  Views in exact mode (instance_capacity = 0) share one host
  * synchronisation; with every view in fixed-capacity mode there is none.

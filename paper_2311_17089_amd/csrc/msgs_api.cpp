@@ -854,6 +854,12 @@ int get_fork_set(msgs_context* c, hipStream_t st, ForkSet** out) {
     *out = it->second;
     return MSGS_OK;
   }
+  // a context keeps at most kMaxForkSets sets (four streams each); calls on
+  // further caller streams run their views on the caller's stream
+  if (c->forks.size() >= (size_t)ForkSet::kMaxSets) {
+    *out = nullptr;
+    return MSGS_OK;
+  }
   // stream and event creation are not stream work: made in relaxed capture
   // mode, so that a first multi-view render under capture can create its set
   hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
@@ -971,7 +977,7 @@ int render_views_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam
       free_all();
       return rc;
     }
-    nfork = std::min(nv, ForkSet::kStreams);
+    nfork = fk ? std::min(nv, ForkSet::kStreams) : 0;
   }
   bool forked = false;
   auto fork = [&]() {
@@ -1190,7 +1196,7 @@ int msgs_render_backward_views(msgs_context* c, const msgs_frame* const* frames,
   if (nviews > 1) {
     int rc0 = get_fork_set(c, st, &fk);
     if (rc0 != MSGS_OK) return rc0;
-    nfork = std::min(nviews, ForkSet::kStreams);
+    if (fk) nfork = std::min(nviews, ForkSet::kStreams);
   }
   float* partial[ForkSet::kStreams] = {};
   uint32_t* wmask[ForkSet::kStreams] = {};

@@ -61,6 +61,7 @@ namespace msgs {
 // slots, never share one), created on first use and kept with the context.
 struct ForkSet {
   static constexpr int kStreams = 4;
+  static constexpr int kMaxSets = 64;  // per context
   hipStream_t s[kStreams] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kStreams] = {};
@@ -151,7 +152,8 @@ int render_internal(msgs_context* c, msgs_scene* s, const msgs_camera* cam,
                     const msgs_render_opts* opts, float* rgb_out, msgs_frame** frame_out,
                     hipStream_t stream);
 constexpr int kMaxViewsPerCall = 64;
-// The fork set of caller stream st (created on first use).
+// The fork set of caller stream st (created on first use); *out = nullptr
+// (no fork) once the context holds kMaxSets sets for other streams.
 int get_fork_set(msgs_context* c, hipStream_t st, ForkSet** out);
 // done_ev (nullable): nv events, event i recorded after view i's last kernel.
 // fork: run the views after the projection on the caller stream's fork

@@ -195,6 +195,27 @@ def test_views_mixed_modes_and_backward_on_another_stream(ctx):
     dsc.close()
 
 
+def test_views_on_many_caller_streams():
+    # a context keeps fork streams for up to 64 caller streams; multi-view
+    # renders on further streams run their views on the caller's stream, with
+    # the same results
+    c = M.Context(0)
+    sc = _scene(97, counts=(3000, 750, 190, 47))
+    dsc = M.DeviceScene(c, sc)
+    views = _views(197, 2, W=96, H=64)
+    ref = [x.cpu().numpy() for x in M.render_views(c, dsc, views)]
+    streams = [torch.cuda.Stream() for _ in range(70)]
+    for i, st in enumerate(streams):
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            got = M.render_views(c, dsc, views)
+        st.synchronize()
+        for v, (a, b) in enumerate(zip(got, ref)):
+            np.testing.assert_array_equal(a.cpu().numpy(), b, err_msg=f"stream {i} view {v}")
+    _say(f"  {len(streams)} caller streams")
+    dsc.close()
+
+
 def test_views_invalid_arguments(ctx):
     sc = G.make_scene([100], 1, 0, [-3.0])
     dsc = M.DeviceScene(ctx, sc)
