@@ -279,7 +279,8 @@ int msgs_render_backward(msgs_context* ctx, const msgs_frame* frame, const float
  * with bit-identical results: the views' contributions are added in view
  * order in fp32.  The per-view compositing adjoints and partial sums run on
  * four streams of the library's own (view i on stream i mod 4) that `stream`
- * forks to and joins back from; the chain rule then runs on `stream`, reading
+ * forks to and joins back from (the same streams, and the same limit of 64
+ * caller streams, as msgs_render_views); the chain rule then runs on `stream`, reading
  * each Gaussian's parameters and writing its gradients once for up to eight
  * views (more views take further passes).
  *   frames   host array of nviews frames of the same scene and context
