@@ -89,6 +89,7 @@ int main(int argc, char** argv) {
   if (hipMalloc((void**)&g_d, gsz * sizeof(float) + 4) != hipSuccess)
     return fail("hipMalloc gradients", -1);
   float* ones = (float*)malloc(npix * 3 * sizeof(float) + 4);
+  if (!ones) return fail("malloc", -1);
   for (size_t i = 0; i < npix * 3; ++i) ones[i] = 1.0f;
   if (hipMemcpy(dl_d, ones, npix * 3 * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
     return fail("hipMemcpy dL", -1);
@@ -104,6 +105,7 @@ int main(int argc, char** argv) {
 
   float* rgb = (float*)malloc(npix * 3 * sizeof(float) + 4);
   float* dop = (float*)malloc(un * sizeof(float) + 4);
+  if (!rgb || !dop) return fail("malloc", -1);
   if (hipMemcpy(rgb, rgb_d, npix * 3 * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(dop, g.opacity, un * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
     return fail("hipMemcpy results", -1);
