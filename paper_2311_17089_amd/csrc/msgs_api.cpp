@@ -283,11 +283,15 @@ void phase2_launch(msgs_frame* f, float* rgb_out, const Phase2Bufs& b) {
   launch_emit(f->order, f->off_d, d_nvis, n, f->count, f->rect, v.Tx, k0, v0, f->emit_base,
               f->capacity ? (uint32_t)I : 0xFFFFFFFFu, f->capacity ? f->ctr : nullptr, st);
   mark(f, 5);
-  radix_sort_pairs(k0, v0, k1, v1, d_inst, I, 0, bits, b.stmp, st, true);
+  // frames of up to 256 tiles sort their tile ids in one pass, which also
+  // writes the tile ranges
+  bool ranges_done = false;
+  radix_sort_pairs(k0, v0, k1, v1, d_inst, I, 0, bits, b.stmp, st, true, f->ranges, ntile,
+                   &ranges_done);
   mark(f, 6);
   f->tkeys = b.ka;
   f->tvals = b.va;
-  launch_ranges(f->tkeys, d_inst, (uint32_t)I, f->ranges, st);
+  if (!ranges_done) launch_ranges(f->tkeys, d_inst, (uint32_t)I, f->ranges, st);
   mark(f, 7);
   launch_blend(f->ranges, f->tvals, f->rec, v, rgb_out, f->T_final, f->n_accum, f->n_last,
                f->ctr + 8, f->ckpt, f->lshift, f->tmax, st);

@@ -124,9 +124,15 @@ size_t radix_tmp_bytes(int64_t nmax, int npass);
 // Stable LSD sort of pairs by key bits [begin_bit, end_bit).  Returns 1 when
 // the result ended in keys_alt / vals_alt, 0 when in keys / vals.  zeroed: the
 // caller has cleared the first radix_zero_words(nmax, npass) words of tmp.
+// ranges (optional, nranges entries, zeroed by the caller): when the sort is
+// one onesweep pass over keys of at most 8 bits from bit 0, that pass also
+// writes ranges[v] = [first, end) of key value v in the sorted list for every
+// v < nranges that occurs, and *ranges_done is set; otherwise it is cleared
+// and the caller computes the ranges itself.
 int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                      const uint32_t* d_n, int64_t nmax, int begin_bit, int end_bit, void* tmp,
-                     hipStream_t st, bool zeroed = false);
+                     hipStream_t st, bool zeroed = false, uint2* ranges = nullptr,
+                     int nranges = 0, bool* ranges_done = nullptr);
 int64_t radix_zero_words(int64_t nmax, int npass);
 // The same stable sort when only the sorted values are needed: they land in
 // vals_final (distinct from vals and vals_alt); keys, vals, keys_alt and

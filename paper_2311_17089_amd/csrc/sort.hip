@@ -349,7 +349,8 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
                                                     const uint32_t* hist,
                                                     unsigned long long* status,
                                                     uint32_t* ticket, const uint32_t* starts,
-                                                    int64_t nblk, SkipPass sk) {
+                                                    int64_t nblk, SkipPass sk, uint2* ranges,
+                                                    int nranges) {
   constexpr int TILE = kBlock * ITEMS;
   __shared__ uint32_t cnt[kBlock / 64][kRadix];
   __shared__ uint32_t ldig[kRadix];
@@ -402,6 +403,10 @@ __global__ __launch_bounds__(kBlock) void k_os_pass(const uint32_t* keys_in,
   const uint32_t hd = hist[threadIdx.x];
   uint32_t gs = block_excl_scan(hd, wtot, htot);
   if (RTS) gs += starts[(int64_t)threadIdx.x * nblk + t];
+  // a one-pass sort of tile ids also gives every tile's range of the sorted
+  // list: its digit's start and count (a tile with no key keeps (0, 0))
+  if (!RTS && ranges && t == 0 && (int)threadIdx.x < nranges && hd)
+    ranges[threadIdx.x] = make_uint2(gs, gs + hd);
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
     const bool valid = i * 64 + lane < remw;
@@ -548,7 +553,9 @@ size_t radix_tmp_bytes(int64_t nmax, int npass) {
 
 int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
                      const uint32_t* d_n, int64_t nmax, int begin_bit, int end_bit, void* tmp,
-                     hipStream_t st, bool zeroed) {
+                     hipStream_t st, bool zeroed, uint2* ranges, int nranges,
+                     bool* ranges_done) {
+  if (ranges_done) *ranges_done = false;
   if (nmax == 0 || end_bit <= begin_bit) return 0;
   const int npass = (end_bit - begin_bit + kRadixBits - 1) / kRadixBits;
   const int items = sort_items(nmax);
@@ -577,11 +584,11 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
       if (items == 16)
         hipLaunchKernelGGL((k_os_pass<16, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                            vin, kout, vout, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
-                           nblk, SkipPass{});
+                           nblk, SkipPass{}, nullptr, 0);
       else
         hipLaunchKernelGGL((k_os_pass<8, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                            vin, kout, vout, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
-                           nblk, SkipPass{});
+                           nblk, SkipPass{}, nullptr, 0);
       uint32_t* tt;
       tt = kin; kin = kout; kout = tt;
       tt = vin; vin = vout; vout = tt;
@@ -594,6 +601,10 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
   const int hgrid = (int)std::min<int64_t>((nmax + 4095) / 4096, kHistBlocks);
   hipLaunchKernelGGL(k_os_hist, dim3(hgrid), dim3(kBlock), 0, st, keys, d_n, nmax, begin_bit,
                      end_bit, ghist);
+  // one pass over keys that start at bit 0: its digit histogram is the count
+  // of every key value, so the pass also writes the value ranges
+  uint2* rg = (ranges && npass == 1 && begin_bit == 0) ? ranges : nullptr;
+  if (rg && ranges_done) *ranges_done = true;
   for (int p = 0; p < npass; ++p) {
     int b, nbits;
     pass_digits(begin_bit, end_bit, p, b, nbits);
@@ -601,12 +612,12 @@ int radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_
       hipLaunchKernelGGL((k_os_pass<16, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                          vin, kout, vout, d_n, nmax, b, nbits, ghist + p * kRadix,
                          status + (int64_t)p * nblk * kRadix, tickets + p, nullptr, nblk,
-                         SkipPass{});
+                         SkipPass{}, rg, nranges);
     else
       hipLaunchKernelGGL((k_os_pass<8, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                          vin, kout, vout, d_n, nmax, b, nbits, ghist + p * kRadix,
                          status + (int64_t)p * nblk * kRadix, tickets + p, nullptr, nblk,
-                         SkipPass{});
+                         SkipPass{}, rg, nranges);
     uint32_t* tt;
     tt = kin; kin = kout; kout = tt;
     tt = vin; vin = vout; vout = tt;
@@ -644,11 +655,11 @@ void radix_sort_values(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint3
       if (items == 16)
         hipLaunchKernelGGL((k_os_pass<16, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                            vin, ko, vo, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
-                           nblk, SkipPass{});
+                           nblk, SkipPass{}, nullptr, 0);
       else
         hipLaunchKernelGGL((k_os_pass<8, true>), dim3((unsigned)nblk), dim3(kBlock), 0, st, kin,
                            vin, ko, vo, d_n, nmax, b, nbits, rowtot, nullptr, nullptr, starts,
-                           nblk, SkipPass{});
+                           nblk, SkipPass{}, nullptr, 0);
       uint32_t* tt;
       tt = kin; kin = kout; kout = tt;
       tt = vin; vin = vout; vout = tt;
@@ -669,12 +680,12 @@ void radix_sort_values(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint3
       hipLaunchKernelGGL((k_os_pass<16, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st,
                          nullptr, nullptr, nullptr, nullptr, d_n, nmax, b, nbits,
                          ghist + p * kRadix, status + (int64_t)p * nblk * kRadix, tickets + p,
-                         nullptr, nblk, sk);
+                         nullptr, nblk, sk, nullptr, 0);
     else
       hipLaunchKernelGGL((k_os_pass<8, false>), dim3((unsigned)nblk), dim3(kBlock), 0, st,
                          nullptr, nullptr, nullptr, nullptr, d_n, nmax, b, nbits,
                          ghist + p * kRadix, status + (int64_t)p * nblk * kRadix, tickets + p,
-                         nullptr, nblk, sk);
+                         nullptr, nblk, sk, nullptr, 0);
   }
 }
 
